@@ -1,0 +1,294 @@
+/*
+ * nbody_oracle.c -- CPU FP64 reference for the direct-sum (particle-particle)
+ * N-body step.  TEST INFRASTRUCTURE ONLY: this file is the checker that the
+ * GPU library is compared against.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it; the product never does.
+ *
+ * It is deliberately plain: scalar double arithmetic, IEEE sqrt and
+ * division, no blocking, no fused multiply-add (built with
+ * -ffp-contract=off), the j sum taken in index order.  Parallelism is over
+ * target particles i only, so every result is independent of the thread
+ * count.  It shares no source with the GPU kernels.
+ *
+ * Paper: Khrapov, Khoperskov & Khoperskov, "New features of parallel
+ * implementation of N-body problems on GPU" (2018).
+ *
+ * Readings taken where the paper is silent or garbled:
+ *  - Eq. (2)'s denominator |r_i - r_j + delta| is the Plummer-softened
+ *    distance sqrt(|r_i - r_j|^2 + delta^2), as the text under Eq. (2) defines.
+ *  - A pair whose softened distance is exactly zero (delta = 0 and coincident
+ *    particles) contributes nothing.
+ *  - Eq. (8) prints the potential term with a plus sign; gravity needs a minus.
+ *  - Eq. (10) is the z-component of L; the full vector is returned.
+ *  - The fixed halo is not in the paper (its disk is fully self-gravitating);
+ *    it is an optional external field: a cored isothermal sphere.
+ *  - The "fourth-order scheme" of the abstract is not named; the triple-jump
+ *    composition of the leapfrog step (Yoshida 1990; Forest & Ruth 1990) is used.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int on;       /* 0: no external field */
+    double v2;    /* asymptotic circular speed squared V_inf^2 */
+    double rc;    /* core radius */
+} orc_halo;
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eqs. (1)-(2): a_i = sum_{j != i} f_ij with
+ *   f_ij = -G m_j (r_i - r_j) / (|r_i - r_j|^2 + delta^2)^{3/2}.
+ * Also, when requested:
+ *   phi_i = -sum_{j != i} G m_j / sqrt(|r_i - r_j|^2 + delta^2)   (potential)
+ *   A_i   =  sum_{j != i} |f_ij|                                 (force scale)
+ * rows == NULL evaluates every i (outputs of length n); otherwise the nrows
+ * listed targets (outputs of length nrows).  reverse_j sums j from n-1 down.
+ */
+static void accel_one(int64_t n, const double *x, const double *y, const double *z,
+                      const double *m, double G, double eps, int64_t i, int reverse_j,
+                      double *oax, double *oay, double *oaz, double *ophi, double *oA) {
+    const double d2 = eps * eps;
+    double ax = 0.0, ay = 0.0, az = 0.0, phi = 0.0, A = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t j = reverse_j ? (n - 1 - k) : k;
+        if (j == i) continue;                       /* Eq. (1): j != i */
+        const double dx = x[i] - x[j];
+        const double dy = y[i] - y[j];
+        const double dz = z[i] - z[j];
+        const double r2 = dx * dx + dy * dy + dz * dz + d2;
+        if (r2 == 0.0) continue;                    /* zero softened distance */
+        const double r = sqrt(r2);
+        const double r3 = r2 * r;
+        const double s = G * m[j] / r3;
+        ax -= s * dx;                               /* f_ij = -G m_j (r_i - r_j) / r^3 */
+        ay -= s * dy;
+        az -= s * dz;
+        phi -= G * m[j] / r;
+        A += s * sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    *oax = ax; *oay = ay; *oaz = az;
+    if (ophi) *ophi = phi;
+    if (oA) *oA = A;
+}
+
+void orc_accel(int64_t n, const double *x, const double *y, const double *z, const double *m,
+               double G, double eps, const int64_t *rows, int64_t nrows, int reverse_j,
+               double *ax, double *ay, double *az, double *phi, double *A, int nthreads) {
+    set_threads(nthreads);
+    const int64_t cnt = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < cnt; ++q) {
+        const int64_t i = rows ? rows[q] : q;
+        accel_one(n, x, y, z, m, G, eps, i, reverse_j, &ax[q], &ay[q], &az[q],
+                  phi ? &phi[q] : NULL, A ? &A[q] : NULL);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cored isothermal halo, density rho0 / (1 + r^2/rc^2), V_inf^2 = 4 pi G rho0 rc^2.
+ * Enclosed mass G M(<r) = V_inf^2 (r - rc atan(r/rc)), so the field is
+ *   a_h = -(G M(<r) / r^3) r_vec = -V_inf^2 (1 - (rc/r) atan(r/rc)) r_vec / r^2
+ * and the potential (zero at infinity is not finite for this profile; the
+ * constant is fixed so that Phi(r) = V_inf^2 [(rc/r) atan(r/rc) + ln(1 + r^2/rc^2)/2])
+ * has dPhi/dr = V_c^2 / r.  Below r = 1e-4 rc the bracket is evaluated from
+ * its Taylor series to avoid cancellation. */
+static double halo_g_over_r(double r, double v2, double rc) {
+    /* returns G M(<r) / r^3 */
+    const double s = r / rc;
+    if (s < 1e-4) {
+        /* 1 - atan(s)/s = s^2/3 - s^4/5 + ... */
+        return v2 / (rc * rc) * (1.0 / 3.0 - s * s / 5.0);
+    }
+    return v2 * (1.0 - atan(s) / s) / (r * r);
+}
+
+static double halo_phi(double r, double v2, double rc) {
+    const double s = r / rc;
+    if (s < 1e-4) {
+        /* atan(s)/s + ln(1+s^2)/2 = 1 + s^2/6 - s^4/20 + ... */
+        return v2 * (1.0 + s * s / 6.0 - s * s * s * s / 20.0);
+    }
+    return v2 * (atan(s) / s + 0.5 * log(1.0 + s * s));
+}
+
+void orc_halo_accel(int64_t n, const double *x, const double *y, const double *z, double v2,
+                    double rc, double *ax, double *ay, double *az, double *phi) {
+    for (int64_t i = 0; i < n; ++i) {
+        const double r = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+        const double g = halo_g_over_r(r, v2, rc);
+        ax[i] = -g * x[i];
+        ay[i] = -g * y[i];
+        az[i] = -g * z[i];
+        if (phi) phi[i] = halo_phi(r, v2, rc);
+    }
+}
+
+/* total acceleration: self-gravity plus the optional halo */
+static void total_accel(int64_t n, const double *x, const double *y, const double *z,
+                        const double *m, double G, double eps, const orc_halo *h,
+                        int reverse_j, double *ax, double *ay, double *az, int nthreads) {
+    orc_accel(n, x, y, z, m, G, eps, NULL, 0, reverse_j, ax, ay, az, NULL, NULL, nthreads);
+    if (h && h->on) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double r = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+            const double g = halo_g_over_r(r, h->v2, h->rc);
+            ax[i] += -g * x[i];
+            ay[i] += -g * y[i];
+            az[i] += -g * z[i];
+        }
+    }
+}
+
+static int64_t g_force_evals = 0;
+int64_t orc_force_evals(void) { return g_force_evals; }
+void orc_reset_force_evals(void) { g_force_evals = 0; }
+
+/* ------------------------------------------------------------------------ */
+/* Section 1, Eqs. (5)-(7): leapfrog kick-drift-kick with one force
+ * evaluation per step.  On entry a must hold the acceleration at r; on
+ * return it holds the acceleration at the final r.
+ *
+ * paper_form = 1 follows the printed predictor / drift / corrector:
+ *   v~ = v + dt a(t);  r += dt/2 (v~ + v);  a(t+dt);  v = (v + v~)/2 + dt/2 a(t+dt)
+ * paper_form = 0 uses the algebraically identical half-kick form:
+ *   v += dt/2 a;  r += dt v;  a(t+dt);  v += dt/2 a(t+dt)
+ */
+static void kdk_once(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                     double *vz, const double *m, double *ax, double *ay, double *az, double G,
+                     double eps, const orc_halo *h, double dt, int paper_form, int reverse_j,
+                     int nthreads) {
+    if (paper_form) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double wx = vx[i] + dt * ax[i];
+            const double wy = vy[i] + dt * ay[i];
+            const double wz = vz[i] + dt * az[i];
+            x[i] += dt / 2.0 * (wx + vx[i]);
+            y[i] += dt / 2.0 * (wy + vy[i]);
+            z[i] += dt / 2.0 * (wz + vz[i]);
+            /* keep (v + v~)/2 in v until the new force is known */
+            vx[i] = (vx[i] + wx) / 2.0;
+            vy[i] = (vy[i] + wy) / 2.0;
+            vz[i] = (vz[i] + wz) / 2.0;
+        }
+    } else {
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += dt / 2.0 * ax[i];
+            vy[i] += dt / 2.0 * ay[i];
+            vz[i] += dt / 2.0 * az[i];
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+        }
+    }
+    total_accel(n, x, y, z, m, G, eps, h, reverse_j, ax, ay, az, nthreads);
+    ++g_force_evals;
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] += dt / 2.0 * ax[i];
+        vy[i] += dt / 2.0 * ay[i];
+        vz[i] += dt / 2.0 * az[i];
+    }
+}
+
+void orc_step_kdk(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                  const double *m, double *ax, double *ay, double *az, double G, double eps,
+                  const orc_halo *h, double dt, int64_t nsteps, int paper_form, int reverse_j,
+                  int nthreads) {
+    for (int64_t s = 0; s < nsteps; ++s)
+        kdk_once(n, x, y, z, vx, vy, vz, m, ax, ay, az, G, eps, h, dt, paper_form, reverse_j,
+                 nthreads);
+}
+
+/* Fourth order: S4(dt) = S2(w1 dt) S2(w0 dt) S2(w1 dt) where S2 is the
+ * leapfrog step above and (w1, w0) satisfy 2 w1 + w0 = 1, 2 w1^3 + w0^3 = 0
+ * (the caller passes them).  Three force evaluations per step. */
+void orc_step_o4(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                 const double *m, double *ax, double *ay, double *az, double G, double eps,
+                 const orc_halo *h, double dt, int64_t nsteps, double w1, double w0,
+                 int reverse_j, int nthreads) {
+    for (int64_t s = 0; s < nsteps; ++s) {
+        kdk_once(n, x, y, z, vx, vy, vz, m, ax, ay, az, G, eps, h, w1 * dt, 0, reverse_j, nthreads);
+        kdk_once(n, x, y, z, vx, vy, vz, m, ax, ay, az, G, eps, h, w0 * dt, 0, reverse_j, nthreads);
+        kdk_once(n, x, y, z, vx, vy, vz, m, ax, ay, az, G, eps, h, w1 * dt, 0, reverse_j, nthreads);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3, Eqs. (8)-(10) and the centre of mass.
+ * out[0]  K    = sum m |v|^2 / 2
+ * out[1]  W    = -(1/2) sum_i sum_{j != i} G m_i m_j / sqrt(|r_i - r_j|^2 + delta^2)
+ * out[2]  Wext = sum m_i Phi_h(r_i)            (0 without halo)
+ * out[3]  E    = K + W + Wext
+ * out[4..6]   P = sum m v
+ * out[7..9]   L = sum m r x v   (Eq. (10) is out[9])
+ * out[10..12] centre of mass sum m r / M
+ * out[13] M    = sum m
+ * Per-particle terms are formed in parallel and summed serially in index
+ * order. */
+void orc_diag(int64_t n, const double *x, const double *y, const double *z, const double *vx,
+              const double *vy, const double *vz, const double *m, double G, double eps,
+              const orc_halo *h, double *out, int nthreads) {
+    set_threads(nthreads);
+    double *w = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    const double d2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[i] - x[j];
+            const double dy = y[i] - y[j];
+            const double dz = z[i] - z[j];
+            const double r2 = dx * dx + dy * dy + dz * dz + d2;
+            if (r2 == 0.0) continue;
+            s += G * m[i] * m[j] / sqrt(r2);
+        }
+        w[i] = s;
+    }
+    double K = 0, W = 0, Wext = 0, P[3] = {0, 0, 0}, L[3] = {0, 0, 0}, C[3] = {0, 0, 0}, M = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        K += m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) / 2.0;
+        W -= w[i] / 2.0;
+        if (h && h->on) {
+            const double r = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+            Wext += m[i] * halo_phi(r, h->v2, h->rc);
+        }
+        P[0] += m[i] * vx[i];
+        P[1] += m[i] * vy[i];
+        P[2] += m[i] * vz[i];
+        L[0] += m[i] * (y[i] * vz[i] - z[i] * vy[i]);
+        L[1] += m[i] * (z[i] * vx[i] - x[i] * vz[i]);
+        L[2] += m[i] * (x[i] * vy[i] - y[i] * vx[i]);
+        C[0] += m[i] * x[i];
+        C[1] += m[i] * y[i];
+        C[2] += m[i] * z[i];
+        M += m[i];
+    }
+    free(w);
+    out[0] = K; out[1] = W; out[2] = Wext; out[3] = K + W + Wext;
+    out[4] = P[0]; out[5] = P[1]; out[6] = P[2];
+    out[7] = L[0]; out[8] = L[1]; out[9] = L[2];
+    out[10] = M > 0 ? C[0] / M : 0.0;
+    out[11] = M > 0 ? C[1] / M : 0.0;
+    out[12] = M > 0 ? C[2] / M : 0.0;
+    out[13] = M;
+}
