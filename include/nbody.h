@@ -1,0 +1,241 @@
+/*
+ * nbody.h -- C ABI of the MI355X direct-sum (particle-particle) N-body library.
+ *
+ * Method: Khrapov, Khoperskov & Khoperskov, "New features of parallel
+ * implementation of N-body problems on GPU", Bull. SUSU MMP 11(1), 2018.
+ *   - softened pair acceleration, Section 1, Eqs. (1)-(2):
+ *       a_i = G sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}
+ *   - kick-drift-kick leapfrog, Section 1, Eqs. (5)-(7), one force
+ *     evaluation per step;
+ *   - a fourth-order scheme (named, not specified, in the abstract): the
+ *     triple-jump composition of the leapfrog step, three evaluations per step;
+ *   - energy, momentum and angular momentum, Section 3, Eqs. (8)-(10).
+ *
+ * Conventions shared by every entry point
+ *   Memory.   Particle arrays are caller-owned DEVICE memory: contiguous
+ *             float64 structure-of-arrays, one element per particle.  The
+ *             library owns only its context, plans and internal scratch.
+ *   Streams.  `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *             default stream).  Every call only enqueues work and returns;
+ *             nothing synchronises the host except the calls documented
+ *             as synchronous (autotune, profile_read).
+ *   Errors.   Arguments are validated before anything is launched: n < 0,
+ *             a NULL array that the call needs, a negative or non-finite
+ *             eps or G, a non-finite dt, an unknown precision, a bad range
+ *             or non-monotone offsets return NB_EINVAL and launch nothing.
+ *             HIP failures return NB_EHIP.  The message of the last
+ *             failure on a context is available from nbody_last_error().
+ *             No C++ exception crosses this boundary.  NaN particle data is
+ *             not checked; it propagates.
+ *   Sizes.    n = 0 is a valid no-op.  n = 1 gives zero self-gravity (plus
+ *             the halo field if enabled).
+ *   Scratch.  Internal scratch grows on first use for a given size; after a
+ *             warm-up call with the largest size, later calls allocate
+ *             nothing (so they may be captured into a HIP graph).
+ *   Threads.  A context is not thread-safe: use one per host thread or lock.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nbody_ctx nbody_ctx;     /* opaque, library-owned */
+typedef struct nbody_batch nbody_batch; /* opaque batched-launch plan */
+
+typedef enum {
+    NB_OK = 0,
+    NB_EINVAL = -1,  /* invalid argument; nothing launched */
+    NB_ENOMEM = -2,  /* device or host allocation failed */
+    NB_EHIP = -3,    /* a HIP runtime call failed */
+    NB_ENOTSUP = -4  /* valid but unsupported request */
+} nbody_status;
+
+/* Arithmetic of the pair sum.
+ *   NB_FP64:  everything in float64; the hardware reciprocal square root is
+ *             refined to full float64 accuracy.
+ *   NB_MIXED: pair separations formed in float64 from the float64 positions
+ *             and then rounded to float32; the pair term in float32; per-target
+ *             sums in float32 over one j tile, then added into float64
+ *             accumulators.  State updates and diagnostics stay float64.
+ *   NB_FP32:  the paper's single precision: positions rounded to float32,
+ *             all pair and accumulation arithmetic and the state updates in
+ *             float32 (results stored back into the float64 arrays). */
+typedef enum { NB_FP64 = 0, NB_MIXED = 1, NB_FP32 = 2 } nbody_prec;
+
+/* One system of n particles.  x..az are device arrays of n doubles.
+ * phi (may be NULL) receives the self-gravity potential
+ *   phi_i = -G sum_{j != i} m_j / sqrt(|r_i - r_j|^2 + eps^2). */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    const double *m;
+    double *ax, *ay, *az;
+    double *phi;
+} nbody_sys;
+
+/* Physical and numerical parameters.  The optional fixed halo is a cored
+ * isothermal sphere with density ~ 1/(1 + r^2/rc^2) centred on the origin:
+ *   a_h(r) = -V^2 (1 - (rc/r) atan(r/rc)) r_vec / r^2,
+ *   Phi_h(r) = V^2 [(rc/r) atan(r/rc) + ln(1 + r^2/rc^2)/2]
+ * (halo_v2 = V^2 > 0, halo_rc = rc > 0).  The paper's disk has no halo. */
+typedef struct {
+    double G;        /* gravitational constant, finite and >= 0 */
+    double eps;      /* Plummer softening length (delta of Eq. (2)), finite and >= 0 */
+    int32_t prec;    /* nbody_prec */
+    int32_t halo;    /* 0: no external field; 1: add the halo above */
+    double halo_v2;
+    double halo_rc;
+} nbody_params;
+
+/* Conserved quantities, Eqs. (8)-(10) with the potential term negative
+ * (gravity is attractive; the printed "+" of Eq. (8) is read as a typo):
+ *   K    = sum m |v|^2 / 2
+ *   W    = -(1/2) sum_i sum_{j != i} G m_i m_j / sqrt(|r_ij|^2 + eps^2)
+ *   Wext = sum m Phi_h(r)          (0 without halo)
+ *   E    = K + W + Wext
+ *   P    = sum m v,  L = sum m r x v (Eq. (10) is L[2]),  com = sum m r / M
+ * Always computed in float64. */
+typedef struct {
+    double K, W, Wext, E;
+    double P[3];
+    double L[3];
+    double com[3];
+    double M;
+} nbody_diag_t;
+
+/* Launch plan of the pair-sum kernel.
+ *   R     targets per lane held in registers (1, 2 or 4)
+ *   block threads per workgroup = j-tile length (128 or 256)
+ *   split number of j chunks summed separately, then reduced in a fixed
+ *         order (>= 1; small systems use it to fill the GPU)
+ *   jsrc  0 = j tiles staged through LDS, 1 = j read through the scalar
+ *         cache straight into SGPR operands */
+typedef struct {
+    int32_t R;
+    int32_t block;
+    int32_t split;
+    int32_t jsrc;
+} nbody_plan;
+
+/* Per-context kernel timing (HIP events around every pair-sum launch). */
+typedef struct {
+    int64_t accel_launches;   /* pair-sum kernel launches timed */
+    double accel_ms;          /* their summed device time */
+    int64_t interactions;     /* sum over those launches of (targets x sources) */
+    int64_t update_launches;  /* kick / drift kernels */
+    double update_ms;
+} nbody_profile_t;
+
+/* ---- context -------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+nbody_status nbody_ctx_create(int device, nbody_ctx **out);
+/* Destroy a context (synchronises its device first).  NULL is a no-op. */
+nbody_status nbody_ctx_destroy(nbody_ctx *ctx);
+/* Message of the last failure on ctx (never NULL; "" if none). */
+const char *nbody_last_error(const nbody_ctx *ctx);
+/* Library version string. */
+const char *nbody_version(void);
+
+/* ---- single system -------------------------------------------------- */
+
+/* Eqs. (1)-(2) (+ halo): overwrite sys->ax/ay/az (and sys->phi when not
+ * NULL) with the acceleration at the current positions.  Reads x, y, z, m. */
+nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+                         void *stream);
+
+/* Same as nbody_accel for the targets i in [i0, i1) only (all n particles
+ * are sources).  Rows [i0, i1) are bitwise equal to those of nbody_accel
+ * under the same plan; the other rows are untouched.  This is one GPU's
+ * share when the targets of one system are split across several GPUs. */
+nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+                              int64_t i0, int64_t i1, void *stream);
+
+/* Eqs. (5)-(7): nsteps leapfrog steps of size dt,
+ *   v += dt/2 a;  r += dt v;  a = accel(r);  v += dt/2 a
+ * (the half-kick form, identical in exact arithmetic to the printed
+ * predictor/corrector).  Precondition: ax/ay/az hold the acceleration at
+ * the current positions (call nbody_accel once first); on return they
+ * hold the acceleration at the final positions.  One force evaluation per
+ * step.  Updates x, y, z, vx, vy, vz, ax, ay, az.  nsteps >= 0. */
+nbody_status nbody_step_kdk(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
+                            int64_t nsteps, void *stream);
+
+/* Fourth order: each step is the composition KDK(w1 dt) KDK(w0 dt) KDK(w1 dt)
+ * with w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1 (Yoshida 1990; Forest & Ruth 1990).
+ * Same precondition and postcondition as nbody_step_kdk; three force
+ * evaluations per step. */
+nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
+                           int64_t nsteps, void *stream);
+
+/* Eqs. (8)-(10): write one nbody_diag_t to DEVICE memory out_dev.  Costs an
+ * O(N^2) float64 potential pass plus O(N) reductions in a fixed order, so
+ * the result is deterministic for a given n.  Does not modify sys. */
+nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+                        nbody_diag_t *out_dev, void *stream);
+
+/* ---- many independent systems in one launch ---------------------------- */
+
+/* flags for nbody_batch_create */
+#define NB_BATCH_GRAPH 1u  /* replay each step from a captured HIP graph */
+
+/* Plan a batch of B independent systems packed back to back in one set of
+ * arrays: system b owns particles [off[b], off[b+1]).  off (B+1 entries,
+ * off[0] = 0, non-decreasing), prm (B entries) and dt (B entries, may be
+ * NULL for accel/diag-only use) are HOST arrays copied into the plan.
+ * Systems never interact.  Systems may use different precisions. */
+nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off,
+                                const nbody_params *prm, const double *dt, uint32_t flags,
+                                nbody_batch **out);
+nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *batch);
+/* The pair-sum plan used for every system of the batch. */
+nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *batch, nbody_plan *out);
+
+/* Pair sums of every system of the batch in one persistent launch per
+ * precision present.  all->n must equal off[B].  Each system's result is
+ * bitwise equal to nbody_accel on that system alone under the plan that
+ * nbody_batch_get_plan reports (split is always 1 in a batch). */
+nbody_status nbody_accel_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
+                                 void *stream);
+/* nsteps KDK steps of every system with its own dt (same contract as
+ * nbody_step_kdk per system). */
+nbody_status nbody_step_kdk_batched(nbody_ctx *ctx, nbody_batch *batch, nbody_sys *all,
+                                    int64_t nsteps, void *stream);
+/* nsteps fourth-order steps of every system. */
+nbody_status nbody_step_o4_batched(nbody_ctx *ctx, nbody_batch *batch, nbody_sys *all,
+                                   int64_t nsteps, void *stream);
+/* B nbody_diag_t records (device memory, B entries) in system order. */
+nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
+                                nbody_diag_t *out_dev, void *stream);
+
+/* ---- launch plans and autotuning --------------------------------------- */
+
+/* Plan the single-system pair sum uses for (prec, n).  Plans are keyed by
+ * (prec, ceil(log2 n)); an untuned key gets a fixed heuristic plan. */
+nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, nbody_plan *out);
+/* Pin the plan for the key of (prec, n) (e.g. one loaded from a cache file). */
+nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, const nbody_plan *plan);
+/* Time every candidate plan on synthetic particles of size n on `device`
+ * scratch memory, pin the fastest for the key of (prec, n) and return it.
+ * Synchronous.  budget_ms > 0 bounds the time spent (at least one
+ * candidate is always timed). */
+nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms,
+                            nbody_plan *out);
+
+/* ---- profiling ---------------------------------------------------------- */
+
+/* Start (on != 0) or stop timing kernel launches with HIP events. */
+nbody_status nbody_profile_enable(nbody_ctx *ctx, int on);
+/* Synchronise on the recorded events, return the totals and reset them. */
+nbody_status nbody_profile_read(nbody_ctx *ctx, nbody_profile_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

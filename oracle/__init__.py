@@ -32,13 +32,13 @@ YOSHIDA_W1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
 YOSHIDA_W0 = 1.0 - 2.0 * YOSHIDA_W1
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
     """Compile the oracle with gcc (seconds)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, src, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Halo(ctypes.Structure):
@@ -57,12 +57,21 @@ _I = ctypes.POINTER(ctypes.c_int64)
 _i64, _dbl, _int = ctypes.c_int64, ctypes.c_double, ctypes.c_int
 
 
-def _load():
+def load_library(path: str | None = None):
+    """(Re)load the oracle library; ``path`` selects another build of the
+    same source (the mutation tests use this to load planted mistakes)."""
+    global _lib
+    _lib = None
+    return _load(path)
+
+
+def _load(path: str | None = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = path or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         lib.orc_accel.argtypes = [_i64, _D, _D, _D, _D, _dbl, _dbl, _I, _i64, _int, _D, _D, _D, _D,
                                   _D, _int]
         lib.orc_halo_accel.argtypes = [_i64, _D, _D, _D, _dbl, _dbl, _D, _D, _D, _D]

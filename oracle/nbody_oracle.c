@@ -106,29 +106,35 @@ void orc_accel(int64_t n, const double *x, const double *y, const double *z, con
 
 /* ------------------------------------------------------------------------ */
 /* Cored isothermal halo, density rho0 / (1 + r^2/rc^2), V_inf^2 = 4 pi G rho0 rc^2.
- * Enclosed mass G M(<r) = V_inf^2 (r - rc atan(r/rc)), so the field is
- *   a_h = -(G M(<r) / r^3) r_vec = -V_inf^2 (1 - (rc/r) atan(r/rc)) r_vec / r^2
- * and the potential (zero at infinity is not finite for this profile; the
- * constant is fixed so that Phi(r) = V_inf^2 [(rc/r) atan(r/rc) + ln(1 + r^2/rc^2)/2])
- * has dPhi/dr = V_c^2 / r.  Below r = 1e-4 rc the bracket is evaluated from
- * its Taylor series to avoid cancellation. */
+ * Enclosed mass G M(<r) = V_inf^2 (r - rc atan(r/rc)), so with s = r/rc
+ *   a_h = -(G M(<r) / r^3) r_vec = -V_inf^2 (1 - atan(s)/s) r_vec / r^2.
+ * The potential diverges logarithmically at infinity, so its constant is
+ * chosen to give Phi(r) = V_inf^2 [atan(s)/s + ln(1 + s^2)/2], which has
+ * dPhi/dr = V_c^2 / r and Phi(0) = V_inf^2.
+ * 1 - atan(s)/s cancels for small s, so below s = 1/2 it is summed from its
+ * Taylor series sum_{k>=1} (-1)^{k+1} s^{2k} / (2k + 1) instead. */
+static double halo_series_over_s2(double s) {
+    /* (1 - atan(s)/s) / s^2 = 1/3 - s^2/5 + s^4/7 - ... for s < 1/2 */
+    const double s2 = s * s;
+    double term = 1.0, sum = 0.0;
+    for (int k = 1; k <= 40; ++k) {
+        sum += ((k % 2) ? term : -term) / (2.0 * k + 1.0);
+        term *= s2;
+    }
+    return sum;
+}
+
 static double halo_g_over_r(double r, double v2, double rc) {
     /* returns G M(<r) / r^3 */
     const double s = r / rc;
-    if (s < 1e-4) {
-        /* 1 - atan(s)/s = s^2/3 - s^4/5 + ... */
-        return v2 / (rc * rc) * (1.0 / 3.0 - s * s / 5.0);
-    }
+    if (s < 0.5) return v2 / (rc * rc) * halo_series_over_s2(s);
     return v2 * (1.0 - atan(s) / s) / (r * r);
 }
 
 static double halo_phi(double r, double v2, double rc) {
     const double s = r / rc;
-    if (s < 1e-4) {
-        /* atan(s)/s + ln(1+s^2)/2 = 1 + s^2/6 - s^4/20 + ... */
-        return v2 * (1.0 + s * s / 6.0 - s * s * s * s / 20.0);
-    }
-    return v2 * (atan(s) / s + 0.5 * log(1.0 + s * s));
+    const double atan_over_s = (s < 0.5) ? 1.0 - s * s * halo_series_over_s2(s) : atan(s) / s;
+    return v2 * (atan_over_s + 0.5 * log1p(s * s));
 }
 
 void orc_halo_accel(int64_t n, const double *x, const double *y, const double *z, double v2,

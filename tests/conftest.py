@@ -16,6 +16,9 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     import oracle
-    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+    alt = os.environ.get("NBODY_ORACLE_LIB")  # a mutated build, see test_oracle_mutations
+    if alt:
+        oracle.load_library(alt)
+    elif not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
     return oracle

@@ -59,16 +59,42 @@ def test_potential_derivative(orc):
 
 
 def test_series_branch_continuity(orc):
+    # the small-radius branch (series below r = rc/2) joins the closed form
     v2, rc = 0.37, 1.3
-    r0 = 1e-4 * rc
-    a_lo, p_lo = _halo(orc, r0 * (1 - 1e-9), v2, rc)
-    a_hi, p_hi = _halo(orc, r0 * (1 + 1e-9), v2, rc)
-    # near the centre the field is harmonic: |a| = V_inf^2 r / (3 rc^2)
-    g_lo = np.linalg.norm(a_lo[0]) / (r0 * (1 - 1e-9))
-    g_hi = np.linalg.norm(a_hi[0]) / (r0 * (1 + 1e-9))
-    assert abs(g_lo / g_hi - 1) < 1e-7
-    assert abs(g_lo / (v2 / (3 * rc * rc)) - 1) < 1e-7
-    assert abs(p_lo[0] / p_hi[0] - 1) < 1e-12
+    r0 = 0.5 * rc
+    a_lo, p_lo = _halo(orc, np.nextafter(r0, 0.0), v2, rc)
+    a_hi, p_hi = _halo(orc, r0, v2, rc)
+    assert abs(np.linalg.norm(a_lo[0]) / np.linalg.norm(a_hi[0]) - 1) < 1e-13
+    assert abs(p_lo[0] / p_hi[0] - 1) < 1e-14
+    # near the centre the field is harmonic: |a| = V_inf^2 r / (3 rc^2) (1 - 3 s^2/5)
+    for s in (1e-9, 1e-5, 1e-3):
+        a, _ = _halo(orc, s * rc, v2, rc)
+        want = v2 * s / (3 * rc) * (1 - 0.6 * s * s + (3.0 / 7) * s ** 4)
+        assert abs(np.linalg.norm(a[0]) / want - 1) < 1e-14
     # at the centre: zero field, Phi(0) = V_inf^2
     a0, p0 = _halo(orc, 0.0, v2, rc)
     assert np.all(a0 == 0) and p0[0] == v2
+
+
+def test_series_matches_high_precision(orc):
+    # 1 - atan(s)/s against an independent extended-precision evaluation
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    v2, rc = 1.0, 1.0
+
+    def atan_dec(s):
+        # atan by its Euler series, convergent for all s: atan s = sum
+        # 2^{2k} (k!)^2 / (2k+1)! * s^{2k+1} / (1+s^2)^{k+1}
+        s = Decimal(s)
+        q = s * s / (1 + s * s)
+        term = s / (1 + s * s)
+        tot = Decimal(0)
+        for k in range(400):
+            tot += term
+            term = term * q * (2 * k + 2) / (2 * k + 3)
+        return tot
+
+    for s in (1e-3, 0.05, 0.3, 0.49, 0.51, 2.0):
+        a, _ = _halo(orc, s, v2, rc, direction=(1.0, 0.0, 0.0))
+        want = float((1 - atan_dec(s) / Decimal(s)) / (Decimal(s) * Decimal(s))) * s
+        assert abs(-a[0][0] / want - 1) < 5e-15, s

@@ -1,0 +1,48 @@
+"""The oracle's pins have teeth: each plausible mistake planted in a copy of
+the oracle source (on the CPU) must make at least one pin test fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "nbody_oracle.c")
+PINS = ["tests/test_oracle_accel.py", "tests/test_oracle_halo.py",
+        "tests/test_oracle_integrators.py", "tests/test_oracle_diag.py"]
+
+# (name, original text, planted mistake); each original occurs in the source
+MUTATIONS = [
+    ("softening dropped", "const double d2 = eps * eps;\n    double ax", "const double d2 = 0.0 * eps;\n    double ax"),
+    ("attraction sign", "ax -= s * dx;", "ax += s * dx;"),
+    ("source mass index", "const double s = G * m[j] / r3;", "const double s = G * m[i] / r3;"),
+    ("distance power", "const double r3 = r2 * r;", "const double r3 = r2;"),
+    ("transposed coordinate", "const double dz = z[i] - z[j];\n        const double r2 = dx * dx + dy * dy + dz * dz + d2;\n        if (r2 == 0.0) continue;                    /* zero",
+     "const double dz = y[i] - y[j];\n        const double r2 = dx * dx + dy * dy + dz * dz + d2;\n        if (r2 == 0.0) continue;                    /* zero"),
+    ("self pair kept", "if (j == i) continue;                       /* Eq. (1): j != i */", ""),
+    ("half-step drift", "x[i] += dt * vx[i];", "x[i] += dt / 2.0 * vx[i];"),
+    ("paper-form corrector", "vx[i] = (vx[i] + wx) / 2.0;", "vx[i] = wx;"),
+    ("fourth-order middle weight", "h, w0 * dt, 0,", "h, w1 * dt, 0,"),
+    ("potential energy double count", "W -= w[i] / 2.0;", "W -= w[i];"),
+    ("kinetic energy factor", "vz[i] * vz[i]) / 2.0;", "vz[i] * vz[i]);"),
+    ("angular momentum cross product", "L[2] += m[i] * (x[i] * vy[i] - y[i] * vx[i]);", "L[2] += m[i] * (x[i] * vx[i] - y[i] * vy[i]);"),
+    ("halo field power", "return v2 * (1.0 - atan(s) / s) / (r * r);", "return v2 * (1.0 - atan(s) / s) / r;"),
+    ("halo potential log factor", "return v2 * (atan_over_s + 0.5 * log1p(s * s));", "return v2 * (atan_over_s + log1p(s * s));"),
+    ("halo core series", "sum += ((k % 2) ? term : -term) / (2.0 * k + 1.0);", "sum += term / (2.0 * k + 1.0);"),
+    ("halo series branch point", "if (s < 0.5) return v2 / (rc * rc) * halo_series_over_s2(s);", "if (s < 0.5) return v2 / (rc * rc) / 3.0;"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,bad", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, orig, bad):
+    import oracle
+    text = open(SRC).read()
+    assert text.count(orig) == 1, f"mutation anchor not unique: {name}"
+    src = tmp_path / "mut.c"
+    src.write_text(text.replace(orig, bad))
+    lib = oracle.build(force=True, src=str(src), out=str(tmp_path / "libmut.so"))
+    env = dict(os.environ, NBODY_ORACLE_LIB=lib, OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"
