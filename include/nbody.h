@@ -40,6 +40,12 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define NBODY_API __attribute__((visibility("default")))
+#else
+#define NBODY_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -135,26 +141,26 @@ typedef struct {
 /* ---- context -------------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
-nbody_status nbody_ctx_create(int device, nbody_ctx **out);
+NBODY_API nbody_status nbody_ctx_create(int device, nbody_ctx **out);
 /* Destroy a context (synchronises its device first).  NULL is a no-op. */
-nbody_status nbody_ctx_destroy(nbody_ctx *ctx);
+NBODY_API nbody_status nbody_ctx_destroy(nbody_ctx *ctx);
 /* Message of the last failure on ctx (never NULL; "" if none). */
-const char *nbody_last_error(const nbody_ctx *ctx);
+NBODY_API const char *nbody_last_error(const nbody_ctx *ctx);
 /* Library version string. */
-const char *nbody_version(void);
+NBODY_API const char *nbody_version(void);
 
 /* ---- single system -------------------------------------------------- */
 
 /* Eqs. (1)-(2) (+ halo): overwrite sys->ax/ay/az (and sys->phi when not
  * NULL) with the acceleration at the current positions.  Reads x, y, z, m. */
-nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+NBODY_API nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                          void *stream);
 
 /* Same as nbody_accel for the targets i in [i0, i1) only (all n particles
  * are sources).  Rows [i0, i1) are bitwise equal to those of nbody_accel
  * under the same plan; the other rows are untouched.  This is one GPU's
  * share when the targets of one system are split across several GPUs. */
-nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+NBODY_API nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                               int64_t i0, int64_t i1, void *stream);
 
 /* Eqs. (5)-(7): nsteps leapfrog steps of size dt,
@@ -164,20 +170,20 @@ nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_
  * the current positions (call nbody_accel once first); on return they
  * hold the acceleration at the final positions.  One force evaluation per
  * step.  Updates x, y, z, vx, vy, vz, ax, ay, az.  nsteps >= 0. */
-nbody_status nbody_step_kdk(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
+NBODY_API nbody_status nbody_step_kdk(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
                             int64_t nsteps, void *stream);
 
 /* Fourth order: each step is the composition KDK(w1 dt) KDK(w0 dt) KDK(w1 dt)
  * with w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1 (Yoshida 1990; Forest & Ruth 1990).
  * Same precondition and postcondition as nbody_step_kdk; three force
  * evaluations per step. */
-nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
+NBODY_API nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
                            int64_t nsteps, void *stream);
 
 /* Eqs. (8)-(10): write one nbody_diag_t to DEVICE memory out_dev.  Costs an
  * O(N^2) float64 potential pass plus O(N) reductions in a fixed order, so
  * the result is deterministic for a given n.  Does not modify sys. */
-nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+NBODY_API nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                         nbody_diag_t *out_dev, void *stream);
 
 /* ---- many independent systems in one launch ---------------------------- */
@@ -190,50 +196,51 @@ nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params
  * off[0] = 0, non-decreasing), prm (B entries) and dt (B entries, may be
  * NULL for accel/diag-only use) are HOST arrays copied into the plan.
  * Systems never interact.  Systems may use different precisions. */
-nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off,
+NBODY_API nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off,
                                 const nbody_params *prm, const double *dt, uint32_t flags,
                                 nbody_batch **out);
-nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *batch);
+NBODY_API nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *batch);
 /* The pair-sum plan used for every system of the batch. */
-nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *batch, nbody_plan *out);
+NBODY_API nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *batch, nbody_plan *out);
 
 /* Pair sums of every system of the batch in one persistent launch per
  * precision present.  all->n must equal off[B].  Each system's result is
  * bitwise equal to nbody_accel on that system alone under the plan that
  * nbody_batch_get_plan reports (split is always 1 in a batch). */
-nbody_status nbody_accel_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
+NBODY_API nbody_status nbody_accel_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
                                  void *stream);
 /* nsteps KDK steps of every system with its own dt (same contract as
  * nbody_step_kdk per system). */
-nbody_status nbody_step_kdk_batched(nbody_ctx *ctx, nbody_batch *batch, nbody_sys *all,
+NBODY_API nbody_status nbody_step_kdk_batched(nbody_ctx *ctx, nbody_batch *batch, nbody_sys *all,
                                     int64_t nsteps, void *stream);
 /* nsteps fourth-order steps of every system. */
-nbody_status nbody_step_o4_batched(nbody_ctx *ctx, nbody_batch *batch, nbody_sys *all,
+NBODY_API nbody_status nbody_step_o4_batched(nbody_ctx *ctx, nbody_batch *batch, nbody_sys *all,
                                    int64_t nsteps, void *stream);
 /* B nbody_diag_t records (device memory, B entries) in system order. */
-nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
+NBODY_API nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
                                 nbody_diag_t *out_dev, void *stream);
 
 /* ---- launch plans and autotuning --------------------------------------- */
 
 /* Plan the single-system pair sum uses for (prec, n).  Plans are keyed by
  * (prec, ceil(log2 n)); an untuned key gets a fixed heuristic plan. */
-nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, nbody_plan *out);
-/* Pin the plan for the key of (prec, n) (e.g. one loaded from a cache file). */
-nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, const nbody_plan *plan);
+NBODY_API nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, nbody_plan *out);
+/* Pin the plan for the key of (prec, n) (e.g. one loaded from a cache file);
+ * plan == NULL removes the pinned plan so the heuristic applies again. */
+NBODY_API nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, const nbody_plan *plan);
 /* Time every candidate plan on synthetic particles of size n on `device`
  * scratch memory, pin the fastest for the key of (prec, n) and return it.
  * Synchronous.  budget_ms > 0 bounds the time spent (at least one
  * candidate is always timed). */
-nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms,
+NBODY_API nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms,
                             nbody_plan *out);
 
 /* ---- profiling ---------------------------------------------------------- */
 
 /* Start (on != 0) or stop timing kernel launches with HIP events. */
-nbody_status nbody_profile_enable(nbody_ctx *ctx, int on);
+NBODY_API nbody_status nbody_profile_enable(nbody_ctx *ctx, int on);
 /* Synchronise on the recorded events, return the totals and reset them. */
-nbody_status nbody_profile_read(nbody_ctx *ctx, nbody_profile_t *out);
+NBODY_API nbody_status nbody_profile_read(nbody_ctx *ctx, nbody_profile_t *out);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,507 @@
+// Pair-sum kernels for gfx950: Eqs. (1)-(2) of Khrapov, Khoperskov &
+// Khoperskov (2018), Section 1,
+//   a_i = G sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}.
+//
+// The paper's GPU kernel (Section 2) copies i and j data to shared memory,
+// synchronises, then sums.  Here, on CDNA4:
+//  * a workgroup of `BLOCK` lanes owns BLOCK*R targets; each lane keeps R
+//    targets and their accumulators in registers (R-way register blocking);
+//  * sources stream through in tiles of BLOCK particles.  With jsrc = 0 a
+//    tile is staged in LDS by one coalesced load per lane and then read
+//    back as a wave-wide broadcast (every lane reads the same address, so
+//    there are no bank conflicts); with jsrc = 1 the sources are read as
+//    wave-uniform values through the scalar cache straight into SGPR
+//    operands of the VALU instructions, with no LDS and no barriers;
+//  * 1/sqrt is the VALU v_rsq instruction.  In float64 its ~2^-24 relative
+//    error is removed by a second-order binomial correction of y^3:
+//      e = r2 y^2 - 1,  (r2 y^2)^{-3/2} = 1 - 3e/2 + 15e^2/8 + O(e^3);
+//  * small systems split the sources into `split` chunks whose partial sums
+//    are reduced afterwards in a fixed order (deterministic, no atomics).
+// There is no MFMA: the pair term is not a dense contraction.
+#include <type_traits>
+
+#include "nbody_internal.h"
+#include "halo.h"
+
+namespace nb {
+namespace {
+
+struct alignas(16) JD { double x, y, z, m; };            // float64 source
+struct alignas(16) JM { double x, y, z; float m, pad; }; // mixed source
+struct alignas(16) JF { float x, y, z, m; };             // float32 source
+
+template <int PREC> struct Tr;
+template <> struct Tr<P_FP64> { using J = JD; using Ti = double; using A = double; };
+template <> struct Tr<P_MIXED> { using J = JM; using Ti = double; using A = float; };
+template <> struct Tr<P_FP32> { using J = JF; using Ti = float; using A = float; };
+
+template <int PREC>
+__device__ __forceinline__ typename Tr<PREC>::J load_src(const State &st, int64_t j, bool ok) {
+    typename Tr<PREC>::J e;
+    if constexpr (PREC == P_FP64) {
+        e.x = ok ? st.x[j] : 0.0; e.y = ok ? st.y[j] : 0.0;
+        e.z = ok ? st.z[j] : 0.0; e.m = ok ? st.m[j] : 0.0;
+    } else if constexpr (PREC == P_MIXED) {
+        e.x = ok ? st.x[j] : 0.0; e.y = ok ? st.y[j] : 0.0;
+        e.z = ok ? st.z[j] : 0.0; e.m = ok ? (float)st.m[j] : 0.0f; e.pad = 0.0f;
+    } else {
+        e.x = ok ? (float)st.x[j] : 0.0f; e.y = ok ? (float)st.y[j] : 0.0f;
+        e.z = ok ? (float)st.z[j] : 0.0f; e.m = ok ? (float)st.m[j] : 0.0f;
+    }
+    return e;
+}
+
+// Per-lane target state and sums.
+template <int PREC, int R>
+struct Lane {
+    using Ti = typename Tr<PREC>::Ti;
+    using F = typename Tr<PREC>::A;          // inner (per-tile) sum type
+    using O = typename std::conditional<PREC == P_FP32, float, double>::type;  // outer sum type
+    Ti xi[R], yi[R], zi[R];
+    int32_t li[R];                           // target index local to the system
+    // Correction coefficients held in registers: gfx9 VOP3 instructions take
+    // no literal operands, so without this the compiler rematerialises them
+    // with two v_mov per pair.
+    double k1875, km15, k0375;
+    F tx[R], ty[R], tz[R], tp[R];            // inner sums
+    O ox[R], oy[R], oz[R], op[R];            // outer sums (MIXED only)
+};
+
+// One source against R targets.
+template <int PREC, int R, int MODE, bool SAFE>
+__device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy, double sz,
+                                         double sm, float fx, float fy, float fz, float fm,
+                                         int32_t lj, double eps2, float eps2f) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (PREC == P_FP64) {
+            const double dx = sx - L.xi[r], dy = sy - L.yi[r], dz = sz - L.zi[r];
+            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+            double y = __builtin_amdgcn_rsq(r2);
+            if constexpr (SAFE) y = (r2 > 0.0) ? y : 0.0;
+            if constexpr (MODE == MODE_PHI || MODE == MODE_ACC_PHI) y = (lj == L.li[r]) ? 0.0 : y;
+            const double y2 = y * y;
+            const double e = __builtin_fma(r2, y2, -1.0);
+            if constexpr (MODE != MODE_PHI) {
+                const double c3 = __builtin_fma(e, __builtin_fma(L.k1875, e, L.km15), 1.0);
+                const double s = ((sm * y) * y2) * c3;
+                L.tx[r] = __builtin_fma(s, dx, L.tx[r]);
+                L.ty[r] = __builtin_fma(s, dy, L.ty[r]);
+                L.tz[r] = __builtin_fma(s, dz, L.tz[r]);
+            }
+            if constexpr (MODE != MODE_ACC) {
+                const double c1 = __builtin_fma(e, __builtin_fma(L.k0375, e, -0.5), 1.0);
+                L.tp[r] = __builtin_fma(sm * y, c1, L.tp[r]);
+            }
+        } else {
+            float dx, dy, dz;
+            if constexpr (PREC == P_MIXED) {
+                dx = (float)(sx - L.xi[r]); dy = (float)(sy - L.yi[r]); dz = (float)(sz - L.zi[r]);
+            } else {
+                dx = fx - L.xi[r]; dy = fy - L.yi[r]; dz = fz - L.zi[r];
+            }
+            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+            float y = __builtin_amdgcn_rsqf(r2);
+            if constexpr (SAFE) y = (r2 > 0.0f) ? y : 0.0f;
+            if constexpr (MODE == MODE_PHI || MODE == MODE_ACC_PHI) y = (lj == L.li[r]) ? 0.0f : y;
+            const float my = fm * y;
+            if constexpr (MODE != MODE_PHI) {
+                const float s = my * (y * y);
+                L.tx[r] = __builtin_fmaf(s, dx, L.tx[r]);
+                L.ty[r] = __builtin_fmaf(s, dy, L.ty[r]);
+                L.tz[r] = __builtin_fmaf(s, dz, L.tz[r]);
+            }
+            if constexpr (MODE != MODE_ACC) L.tp[r] += my;
+        }
+    }
+}
+
+template <int PREC, int R>
+__device__ __forceinline__ void flush(Lane<PREC, R> &L) {
+    if constexpr (PREC == P_MIXED) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            L.ox[r] += (double)L.tx[r]; L.oy[r] += (double)L.ty[r];
+            L.oz[r] += (double)L.tz[r]; L.op[r] += (double)L.tp[r];
+            L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0.0f;
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T in_vgpr(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+template <int PREC, int R>
+__device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int64_t ib,
+                                          int64_t ilim, int64_t sys_off, int BLOCK) {
+    const int t = threadIdx.x;
+    if constexpr (PREC == P_FP64) {
+        L.k1875 = in_vgpr(1.875);
+        L.km15 = in_vgpr(-1.5);
+        L.k0375 = in_vgpr(0.375);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = ib + (int64_t)r * BLOCK + t;
+        const bool ok = i < ilim;
+        L.xi[r] = ok ? (typename Tr<PREC>::Ti)st.x[i] : 0;
+        L.yi[r] = ok ? (typename Tr<PREC>::Ti)st.y[i] : 0;
+        L.zi[r] = ok ? (typename Tr<PREC>::Ti)st.z[i] : 0;
+        L.li[r] = (int32_t)(i - sys_off);
+        L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0;
+        L.ox[r] = L.oy[r] = L.oz[r] = L.op[r] = 0;
+    }
+}
+
+// Sum sources [jb, je) (global indices; the system starts at sys_off) into L.
+// LDS-staged source tiles of BLOCK particles.
+template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
+__device__ __forceinline__ void sweep_lds(Lane<PREC, R> &L, const State &st, int64_t jb,
+                                          int64_t je, int64_t sys_off, double eps2, float eps2f,
+                                          typename Tr<PREC>::J *tile) {
+    const int t = threadIdx.x;
+    for (int64_t jt = jb; jt < je; jt += BLOCK) {
+        const int64_t j = jt + t;
+        tile[t] = load_src<PREC>(st, j, j < je);
+        __syncthreads();
+        const int32_t lj0 = (int32_t)(jt - sys_off);
+#pragma unroll 4
+        for (int k = 0; k < BLOCK; ++k) {
+            const typename Tr<PREC>::J e = tile[k];
+            if constexpr (PREC == P_FP32)
+                interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, e.x, e.y, e.z, e.m, lj0 + k, eps2, eps2f);
+            else if constexpr (PREC == P_MIXED)
+                interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, 0, 0, 0, 0, e.m, lj0 + k, eps2, eps2f);
+            else
+                interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, e.m, 0, 0, 0, 0, lj0 + k, eps2, eps2f);
+        }
+        flush(L);
+        __syncthreads();
+    }
+}
+
+// Same sum with sources read as wave-uniform values (scalar loads into
+// SGPRs).  Groups of U sources; the tail is summed one source at a time so
+// nothing past je is read.
+template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
+__device__ __forceinline__ void sweep_scalar(Lane<PREC, R> &L, const State &st, int64_t jb,
+                                             int64_t je, int64_t sys_off, double eps2,
+                                             float eps2f) {
+    using CD = const __attribute__((address_space(4))) double;
+    CD *X = (CD *)st.x;
+    CD *Y = (CD *)st.y;
+    CD *Z = (CD *)st.z;
+    CD *M = (CD *)st.m;
+    constexpr int U = 8;
+    int64_t j = jb;
+    int64_t flush_at = jb + BLOCK;
+    for (; j + U <= je; j += U) {
+        double sx[U], sy[U], sz[U], sm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { sx[u] = X[j + u]; sy[u] = Y[j + u]; sz[u] = Z[j + u]; sm[u] = M[j + u]; }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t lj = (int32_t)(j + u - sys_off);
+            if constexpr (PREC == P_FP32)
+                interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, (float)sx[u], (float)sy[u], (float)sz[u], (float)sm[u], lj, eps2, eps2f);
+            else if constexpr (PREC == P_MIXED)
+                interact<PREC, R, MODE, SAFE>(L, sx[u], sy[u], sz[u], 0, 0, 0, 0, (float)sm[u], lj, eps2, eps2f);
+            else
+                interact<PREC, R, MODE, SAFE>(L, sx[u], sy[u], sz[u], sm[u], 0, 0, 0, 0, lj, eps2, eps2f);
+        }
+        if (j + U >= flush_at) { flush(L); flush_at += BLOCK; }
+    }
+    for (; j < je; ++j) {
+        const double sx = X[j], sy = Y[j], sz = Z[j], sm = M[j];
+        const int32_t lj = (int32_t)(j - sys_off);
+        if constexpr (PREC == P_FP32)
+            interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, (float)sx, (float)sy, (float)sz, (float)sm, lj, eps2, eps2f);
+        else if constexpr (PREC == P_MIXED)
+            interact<PREC, R, MODE, SAFE>(L, sx, sy, sz, 0, 0, 0, 0, (float)sm, lj, eps2, eps2f);
+        else
+            interact<PREC, R, MODE, SAFE>(L, sx, sy, sz, sm, 0, 0, 0, 0, lj, eps2, eps2f);
+    }
+    flush(L);
+}
+
+// Raw sums of lane slot r (outer for MIXED, inner otherwise).
+template <int PREC, int R>
+__device__ __forceinline__ void raw(const Lane<PREC, R> &L, int r, double &sx, double &sy,
+                                   double &sz, double &sp) {
+    if constexpr (PREC == P_MIXED) { sx = L.ox[r]; sy = L.oy[r]; sz = L.oz[r]; sp = L.op[r]; }
+    else { sx = L.tx[r]; sy = L.ty[r]; sz = L.tz[r]; sp = L.tp[r]; }
+}
+
+// Final acceleration of target i from its raw sums: G * sum (+ halo), the
+// potential -G * sum, and the optional closing half kick.
+template <int PREC, int MODE>
+__device__ __forceinline__ void finish(const State &st, const SysConst &sc, int64_t i, double sx,
+                                       double sy, double sz, double sp, int kick, double hdt) {
+    if constexpr (MODE != MODE_ACC) st.phi[i] = (PREC == P_FP32) ? (double)(-(float)sc.G * (float)sp) : -sc.G * sp;
+    if constexpr (MODE == MODE_PHI) return;
+    double ax, ay, az;
+    if constexpr (PREC == P_FP32) {
+        const float g = (float)sc.G;
+        ax = g * (float)sx; ay = g * (float)sy; az = g * (float)sz;
+    } else {
+        ax = sc.G * sx; ay = sc.G * sy; az = sc.G * sz;
+    }
+    if (sc.halo) {
+        const double x = st.x[i], y = st.y[i], z = st.z[i];
+        const double g = halo_g_over_r3(x * x + y * y + z * z, sc.halo_v2, sc.halo_rc);
+        ax = __builtin_fma(-g, x, ax); ay = __builtin_fma(-g, y, ay); az = __builtin_fma(-g, z, az);
+        if constexpr (PREC == P_FP32) { ax = (float)ax; ay = (float)ay; az = (float)az; }
+    }
+    st.ax[i] = ax; st.ay[i] = ay; st.az[i] = az;
+    if (kick) {
+        if constexpr (PREC == P_FP32) {
+            const float h = (float)hdt;
+            st.vx[i] = __builtin_fmaf(h, (float)ax, (float)st.vx[i]);
+            st.vy[i] = __builtin_fmaf(h, (float)ay, (float)st.vy[i]);
+            st.vz[i] = __builtin_fmaf(h, (float)az, (float)st.vz[i]);
+        } else {
+            st.vx[i] = __builtin_fma(hdt, ax, st.vx[i]);
+            st.vy[i] = __builtin_fma(hdt, ay, st.vy[i]);
+            st.vz[i] = __builtin_fma(hdt, az, st.vz[i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Single system: grid (ceil((i1 - i0) / (BLOCK R)), split).
+template <int PREC, int R, int BLOCK, int MODE, bool SAFE, int JSRC>
+__global__ __launch_bounds__(BLOCK) void k_pair(PairLaunch P, int64_t chunk) {
+    __shared__ typename Tr<PREC>::J tile[JSRC == 0 ? BLOCK : 1];
+    const int64_t ib = P.i0 + (int64_t)blockIdx.x * (BLOCK * R);
+    const int64_t jb = (int64_t)blockIdx.y * chunk;
+    const int64_t je = (jb + chunk < P.sc.n) ? jb + chunk : P.sc.n;
+    Lane<PREC, R> L;
+    lane_init<PREC, R>(L, P.st, ib, P.i1, 0, BLOCK);
+    if constexpr (JSRC == 0)
+        sweep_lds<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f, tile);
+    else
+        sweep_scalar<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f);
+    const int64_t rows = P.i1 - P.i0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = ib + (int64_t)r * BLOCK + threadIdx.x;
+        if (i >= P.i1) continue;
+        double sx, sy, sz, sp;
+        raw<PREC, R>(L, r, sx, sy, sz, sp);
+        if (P.split > 1) {
+            double *q = P.part + (int64_t)blockIdx.y * 4 * rows + (i - P.i0);
+            q[0] = sx; q[rows] = sy; q[2 * rows] = sz; q[3 * rows] = sp;
+        } else {
+            finish<PREC, MODE>(P.st, P.sc, i, sx, sy, sz, sp, P.kick, P.hdt);
+        }
+    }
+}
+
+// Fixed-order reduction of the split partial sums.
+template <int PREC, int MODE>
+__global__ __launch_bounds__(256) void k_pair_reduce(PairLaunch P) {
+    const int64_t rows = P.i1 - P.i0;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= rows) return;
+    const double *p = P.part + q;
+    double sx, sy, sz, sp;
+    if constexpr (PREC == P_FP32) {
+        float fx = 0, fy = 0, fz = 0, fp = 0;
+        for (int s = 0; s < P.split; ++s) {
+            const double *b = p + (int64_t)s * 4 * rows;
+            fx += (float)b[0]; fy += (float)b[rows]; fz += (float)b[2 * rows]; fp += (float)b[3 * rows];
+        }
+        sx = fx; sy = fy; sz = fz; sp = fp;
+    } else {
+        sx = sy = sz = sp = 0;
+        for (int s = 0; s < P.split; ++s) {
+            const double *b = p + (int64_t)s * 4 * rows;
+            sx += b[0]; sy += b[rows]; sz += b[2 * rows]; sp += b[3 * rows];
+        }
+    }
+    finish<PREC, MODE>(P.st, P.sc, P.i0 + q, sx, sy, sz, sp, P.kick, P.hdt);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent kernel: each workgroup walks the work list with a
+// fixed stride; an item is one tile of BLOCK*R targets of one system
+// against all sources of that system.
+template <int PREC, int R, int BLOCK, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_pair_batched(BatchLaunch B) {
+    __shared__ typename Tr<PREC>::J tile[BLOCK];
+    for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
+        const WorkItem it = B.items[w];
+        const SysConst sc = B.sys[it.sys];
+        const int64_t ilim = sc.off + sc.n;
+        Lane<PREC, R> L;
+        lane_init<PREC, R>(L, B.st, it.i0, ilim, sc.off, BLOCK);
+        const bool safe = (PREC == P_FP64) ? sc.safe64 : sc.safe32;
+        if (safe)
+            sweep_lds<PREC, R, BLOCK, MODE, true>(L, B.st, sc.off, ilim, sc.off, sc.eps2, sc.eps2f, tile);
+        else
+            sweep_lds<PREC, R, BLOCK, MODE, false>(L, B.st, sc.off, ilim, sc.off, sc.eps2, sc.eps2f, tile);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = it.i0 + (int64_t)r * BLOCK + threadIdx.x;
+            if (i >= ilim) continue;
+            double sx, sy, sz, sp;
+            raw<PREC, R>(L, r, sx, sy, sz, sp);
+            finish<PREC, MODE>(B.st, sc, i, sx, sy, sz, sp, B.kick_scale != 0.0,
+                               0.5 * B.kick_scale * sc.dt);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch tables.
+template <int PREC, int R, int BLOCK, int MODE, int JSRC>
+hipError_t go_pair(const PairLaunch &P, hipStream_t s) {
+    const int64_t rows = P.i1 - P.i0;
+    const int64_t per = (int64_t)BLOCK * R;
+    const int64_t nbx = (rows + per - 1) / per;
+    const int64_t per_chunk = (P.sc.n + P.split - 1) / P.split;
+    const int64_t chunk = ((per_chunk + BLOCK - 1) / BLOCK) * BLOCK;
+    if (nbx <= 0) return hipSuccess;
+    dim3 grid((unsigned)nbx, (unsigned)P.split);
+    const bool safe = (PREC == P_FP64) ? P.sc.safe64 : P.sc.safe32;
+    if (safe)
+        hipLaunchKernelGGL((k_pair<PREC, R, BLOCK, MODE, true, JSRC>), grid, dim3(BLOCK), 0, s, P, chunk);
+    else
+        hipLaunchKernelGGL((k_pair<PREC, R, BLOCK, MODE, false, JSRC>), grid, dim3(BLOCK), 0, s, P, chunk);
+    return hipGetLastError();
+}
+
+template <int PREC, int MODE, int JSRC>
+hipError_t pick_rb(const PairLaunch &P, hipStream_t s) {
+    if constexpr (MODE != MODE_ACC) {
+        // potential variants: one fixed shape
+        if (P.R == 1 && P.block == 256) return go_pair<PREC, 1, 256, MODE, JSRC>(P, s);
+        return hipErrorInvalidValue;
+    } else {
+        switch (P.block * 8 + P.R) {
+            case 128 * 8 + 1: return go_pair<PREC, 1, 128, MODE, JSRC>(P, s);
+            case 128 * 8 + 2: return go_pair<PREC, 2, 128, MODE, JSRC>(P, s);
+            case 128 * 8 + 4: return go_pair<PREC, 4, 128, MODE, JSRC>(P, s);
+            case 256 * 8 + 1: return go_pair<PREC, 1, 256, MODE, JSRC>(P, s);
+            case 256 * 8 + 2: return go_pair<PREC, 2, 256, MODE, JSRC>(P, s);
+            case 256 * 8 + 4: return go_pair<PREC, 4, 256, MODE, JSRC>(P, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+template <int PREC, int MODE>
+hipError_t pick_jsrc(const PairLaunch &P, hipStream_t s) {
+    if (P.jsrc == 1) return pick_rb<PREC, MODE, 1>(P, s);
+    return pick_rb<PREC, MODE, 0>(P, s);
+}
+
+template <int PREC>
+hipError_t pick_mode(const PairLaunch &P, hipStream_t s) {
+    switch (P.mode) {
+        case MODE_ACC: return pick_jsrc<PREC, MODE_ACC>(P, s);
+        case MODE_ACC_PHI: return pick_jsrc<PREC, MODE_ACC_PHI>(P, s);
+        case MODE_PHI: return pick_jsrc<PREC, MODE_PHI>(P, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int MODE>
+hipError_t go_reduce(const PairLaunch &P, hipStream_t s) {
+    const int64_t rows = P.i1 - P.i0;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pair_reduce<PREC, MODE>), dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t reduce_mode(const PairLaunch &P, hipStream_t s) {
+    switch (P.mode) {
+        case MODE_ACC: return go_reduce<PREC, MODE_ACC>(P, s);
+        case MODE_ACC_PHI: return go_reduce<PREC, MODE_ACC_PHI>(P, s);
+        case MODE_PHI: return go_reduce<PREC, MODE_PHI>(P, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int R, int BLOCK, int MODE>
+hipError_t go_batched(const BatchLaunch &B, hipStream_t s) {
+    if (B.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pair_batched<PREC, R, BLOCK, MODE>), dim3((unsigned)B.grid), dim3(BLOCK), 0, s, B);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t batched_prec(const BatchLaunch &B, hipStream_t s) {
+    if (B.block != 256) return hipErrorInvalidValue;
+    if (B.mode == MODE_PHI) return (B.R == 1) ? go_batched<PREC, 1, 256, MODE_PHI>(B, s) : hipErrorInvalidValue;
+    if (B.mode != MODE_ACC) return hipErrorInvalidValue;
+    switch (B.R) {
+        case 1: return go_batched<PREC, 1, 256, MODE_ACC>(B, s);
+        case 2: return go_batched<PREC, 2, 256, MODE_ACC>(B, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int R, int MODE>
+int occ_of() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_batched<PREC, R, 256, MODE>, 256, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int PREC>
+int occ_prec(int R, int mode) {
+    if (mode == MODE_PHI) return occ_of<PREC, 1, MODE_PHI>();
+    return R == 2 ? occ_of<PREC, 2, MODE_ACC>() : occ_of<PREC, 1, MODE_ACC>();
+}
+
+}  // namespace
+
+int pair_batched_occupancy(int prec, int R, int block, int mode) {
+    (void)block;
+    switch (prec) {
+        case P_FP64: return occ_prec<P_FP64>(R, mode);
+        case P_MIXED: return occ_prec<P_MIXED>(R, mode);
+        default: return occ_prec<P_FP32>(R, mode);
+    }
+}
+
+bool pair_config_supported(int prec, int R, int block, int jsrc, int mode) {
+    if (prec < 0 || prec > 2 || (jsrc != 0 && jsrc != 1)) return false;
+    if (mode != MODE_ACC) return R == 1 && block == 256;
+    return (block == 128 || block == 256) && (R == 1 || R == 2 || R == 4);
+}
+
+hipError_t launch_pair(const PairLaunch &P, hipStream_t s) {
+    switch (P.sc.prec) {
+        case P_FP64: return pick_mode<P_FP64>(P, s);
+        case P_MIXED: return pick_mode<P_MIXED>(P, s);
+        case P_FP32: return pick_mode<P_FP32>(P, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pair_reduce(const PairLaunch &P, hipStream_t s) {
+    switch (P.sc.prec) {
+        case P_FP64: return reduce_mode<P_FP64>(P, s);
+        case P_MIXED: return reduce_mode<P_MIXED>(P, s);
+        case P_FP32: return reduce_mode<P_FP32>(P, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pair_batched(const BatchLaunch &B, hipStream_t s) {
+    switch (B.prec) {
+        case P_FP64: return batched_prec<P_FP64>(B, s);
+        case P_MIXED: return batched_prec<P_MIXED>(B, s);
+        case P_FP32: return batched_prec<P_FP32>(B, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nb

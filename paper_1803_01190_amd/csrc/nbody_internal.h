@@ -1,0 +1,99 @@
+// Internal interfaces between the host runtime and the gfx950 kernels.
+// Not part of the public ABI (include/nbody.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace nb {
+
+enum Prec { P_FP64 = 0, P_MIXED = 1, P_FP32 = 2 };
+// MODE_ACC: accelerations; MODE_ACC_PHI: accelerations + potential;
+// MODE_PHI: potential only (the diagnostic pass).
+enum Mode { MODE_ACC = 0, MODE_ACC_PHI = 1, MODE_PHI = 2 };
+
+// Per-system constants read by the kernels (single launch: passed by value;
+// batched launch: one entry per system in device memory).
+struct SysConst {
+    int64_t off;       // first particle of the system in the packed arrays
+    int64_t n;         // number of particles
+    double G;
+    double eps2;       // softening squared (float64)
+    float eps2f;       // softening squared rounded to float32
+    int32_t safe64;    // 1: eps2 is not a normal float64, so a zero softened
+                       //    distance is possible and must be masked
+    int32_t safe32;    // same test for eps2f as a float32
+    int32_t halo;
+    int32_t prec;
+    int32_t pad;
+    double halo_v2, halo_rc;
+    double dt;         // step of this system (batched integrators)
+};
+
+// Device pointers of the packed structure-of-arrays state.
+struct State {
+    double *x, *y, *z;
+    const double *m;
+    double *ax, *ay, *az, *phi;
+    double *vx, *vy, *vz;
+};
+
+// One single-system pair-sum launch: targets [i0, i1), sources [0, n).
+struct PairLaunch {
+    State st;
+    SysConst sc;
+    int64_t i0, i1;
+    int32_t R, block, split, jsrc, mode;
+    double hdt;        // > 0 (or != 0): fuse the closing half kick v += hdt a
+    int32_t kick;
+    double *part;      // split > 1: [split][4][i1 - i0] partial sums
+};
+
+// One work item of a batched launch: a tile of targets of one system.
+struct WorkItem {
+    int32_t sys;
+    int32_t pad;
+    int64_t i0;        // first target (global index) of the tile
+};
+
+struct BatchLaunch {
+    State st;
+    const SysConst *sys;      // device, one per system
+    const WorkItem *items;    // device, sorted by cost (largest first)
+    int32_t nitems;
+    int32_t prec, mode, R, block;
+    int32_t grid;             // persistent workgroups
+    double kick_scale;        // closing half kick v += kick_scale * dt_sys * a (0: none)
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_pair(const PairLaunch &L, hipStream_t s);
+hipError_t launch_pair_reduce(const PairLaunch &L, hipStream_t s);
+hipError_t launch_pair_batched(const BatchLaunch &L, hipStream_t s);
+bool pair_config_supported(int prec, int R, int block, int jsrc, int mode);
+// resident workgroups per CU of the batched kernel for (prec, R, block, mode)
+int pair_batched_occupancy(int prec, int R, int block, int mode);
+
+// v += h a; x += dt v   over [0, n)  (fp32 != 0: float32 arithmetic)
+hipError_t launch_kick_drift(const State &st, int64_t n, double h, double dt, int fp32,
+                             hipStream_t s);
+// v += h a over [0, n)
+hipError_t launch_kick(const State &st, int64_t n, double h, int fp32, hipStream_t s);
+// batched forms: each particle uses the dt of its system (scaled by w)
+hipError_t launch_kick_drift_batched(const State &st, const int64_t *off_dev,
+                                     const SysConst *sys, int32_t B, int64_t ntot, double w,
+                                     hipStream_t s);
+hipError_t launch_kick_batched(const State &st, const int64_t *off_dev, const SysConst *sys,
+                               int32_t B, int64_t ntot, double w, hipStream_t s);
+
+// Diagnostics: one workgroup per system reduces K, W (from phi), Wext, P, L,
+// centre of mass and M in a fixed order and writes 14 doubles per system.
+hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst *sys,
+                              int32_t B, double *out, hipStream_t s);
+
+// Small utilities.
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// write one SysConst into device memory (graph-capturable, no host staging)
+hipError_t launch_set_sysconst(SysConst *dst, const SysConst &v, hipStream_t s);
+
+}  // namespace nb

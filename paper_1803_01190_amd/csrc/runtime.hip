@@ -1,0 +1,862 @@
+// Host runtime behind include/nbody.h: contexts, argument validation, launch
+// plans and their autotuner, batched work lists, HIP-graph replay of
+// batched steps, kernel timing, and the integrators' launch sequences.
+//
+// Integrators (Khrapov, Khoperskov & Khoperskov 2018):
+//   KDK leapfrog, Section 1, Eqs. (5)-(7), in half-kick form, one force
+//   evaluation per step:  kick_drift(dt) ; pair sum with fused closing kick.
+//   Fourth order (named in the abstract, unspecified): triple jump
+//   KDK(w1 dt) KDK(w0 dt) KDK(w1 dt), w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "nbody.h"
+#include "nbody_internal.h"
+
+using namespace nb;
+
+struct nbody_ctx {
+    int device = 0;
+    int cus = 256;
+    std::string err;
+    // grow-only device scratch
+    double *part = nullptr;
+    size_t part_cap = 0;   // doubles
+    double *phi = nullptr;
+    size_t phi_cap = 0;    // doubles
+    SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
+    hipStream_t cap = nullptr; // capture stream for batched graphs
+    std::map<std::pair<int, int>, nbody_plan> plans;
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_free;
+    struct Rec { hipEvent_t a, b; int kind; int64_t inter; };
+    std::vector<Rec> recs;
+};
+
+struct nbody_batch {
+    int32_t B = 0;
+    uint32_t flags = 0;
+    int64_t ntot = 0;
+    std::vector<int64_t> off;
+    std::vector<SysConst> sc;
+    int64_t *off_dev = nullptr;
+    SysConst *sc_dev = nullptr;
+    int R = 1, block = 256;
+    // work lists: one per precision for the pair sum, one (all systems,
+    // float64) for the potential pass of the diagnostics
+    WorkItem *items[3] = {nullptr, nullptr, nullptr};
+    int32_t nitems[3] = {0, 0, 0};
+    WorkItem *items_all = nullptr;
+    int32_t nitems_all = 0;
+    int32_t grid[3] = {0, 0, 0};   // persistent workgroups per precision
+    int32_t grid_all = 0;
+    int any_fp32 = 0;
+    // graph cache: key = state pointers + scheme
+    struct Graph { State st; int scheme; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
+};
+
+namespace {
+
+constexpr double kW1 = 1.3512071919596578;   // 1 / (2 - 2^(1/3))
+constexpr double kW0 = -1.7024143839193155;  // 1 - 2 w1
+
+struct DevGuard {
+    int old = -1;
+    bool ok = true;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        if (old != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DevGuard() {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+nbody_status fail(nbody_ctx *ctx, nbody_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+nbody_status fail(nbody_ctx *ctx, nbody_status st, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+nbody_status hipfail(nbody_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, NB_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHECK(ctx, expr)                                           \
+    do {                                                              \
+        hipError_t e__ = (expr);                                      \
+        if (e__ != hipSuccess) return hipfail((ctx), e__, #expr);     \
+    } while (0)
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+nbody_status check_params(nbody_ctx *ctx, const nbody_params *p) {
+    if (!p) return fail(ctx, NB_EINVAL, "params is NULL");
+    if (!is_finite(p->G) || p->G < 0) return fail(ctx, NB_EINVAL, "G must be finite and >= 0");
+    if (!is_finite(p->eps) || p->eps < 0) return fail(ctx, NB_EINVAL, "eps must be finite and >= 0");
+    if (p->prec < NB_FP64 || p->prec > NB_FP32) return fail(ctx, NB_EINVAL, "unknown precision %d", p->prec);
+    if (p->halo != 0 && p->halo != 1) return fail(ctx, NB_EINVAL, "halo must be 0 or 1");
+    if (p->halo && (!is_finite(p->halo_v2) || p->halo_v2 <= 0 || !is_finite(p->halo_rc) || p->halo_rc <= 0))
+        return fail(ctx, NB_EINVAL, "halo_v2 and halo_rc must be finite and > 0");
+    return NB_OK;
+}
+
+nbody_status check_sys(nbody_ctx *ctx, const nbody_sys *s, bool need_v) {
+    if (!s) return fail(ctx, NB_EINVAL, "sys is NULL");
+    if (s->n < 0) return fail(ctx, NB_EINVAL, "n must be >= 0 (got %lld)", (long long)s->n);
+    if (s->n > INT32_MAX) return fail(ctx, NB_EINVAL, "n must be < 2^31 (got %lld)", (long long)s->n);
+    if (s->n == 0) return NB_OK;
+    if (!s->x || !s->y || !s->z || !s->m || !s->ax || !s->ay || !s->az)
+        return fail(ctx, NB_EINVAL, "a position, mass or acceleration array is NULL");
+    if (need_v && (!s->vx || !s->vy || !s->vz)) return fail(ctx, NB_EINVAL, "a velocity array is NULL");
+    return NB_OK;
+}
+
+SysConst make_sysconst(const nbody_params *p, int64_t off, int64_t n, double dt) {
+    SysConst c{};
+    c.off = off;
+    c.n = n;
+    c.G = p->G;
+    c.eps2 = p->eps * p->eps;
+    c.eps2f = (float)c.eps2;
+    c.safe64 = !(c.eps2 >= 2.2250738585072014e-308);
+    c.safe32 = !(c.eps2f >= 1.17549435e-38f);
+    c.halo = p->halo;
+    c.prec = p->prec;
+    c.halo_v2 = p->halo_v2;
+    c.halo_rc = p->halo_rc;
+    c.dt = dt;
+    return c;
+}
+
+State make_state(const nbody_sys *s) {
+    State st{};
+    st.x = s->x; st.y = s->y; st.z = s->z; st.m = s->m;
+    st.ax = s->ax; st.ay = s->ay; st.az = s->az; st.phi = s->phi;
+    st.vx = s->vx; st.vy = s->vy; st.vz = s->vz;
+    return st;
+}
+
+int ilog2_ceil(int64_t n) {
+    int k = 0;
+    while (k < 62 && (int64_t(1) << k) < n) ++k;
+    return k;
+}
+
+nbody_plan heuristic_plan(const nbody_ctx *ctx, int prec, int64_t n) {
+    (void)prec;
+    nbody_plan p{2, 256, 1, 0};
+    const int64_t want = 2LL * ctx->cus;  // at least two workgroups per CU
+    if ((n + 511) / 512 < want) p.R = 1;
+    const int64_t nblk = (n + (int64_t)p.block * p.R - 1) / ((int64_t)p.block * p.R);
+    while (nblk * p.split < want && n / (2LL * p.split) >= 2LL * p.block && p.split < 64) p.split *= 2;
+    return p;
+}
+
+nbody_plan plan_for(nbody_ctx *ctx, int prec, int64_t n) {
+    auto it = ctx->plans.find({prec, ilog2_ceil(n)});
+    if (it != ctx->plans.end()) return it->second;
+    return heuristic_plan(ctx, prec, n);
+}
+
+nbody_status ensure(nbody_ctx *ctx, double **buf, size_t *cap, size_t need) {
+    if (need <= *cap) return NB_OK;
+    if (*buf) {
+        HIPCHECK(ctx, hipDeviceSynchronize());
+        HIPCHECK(ctx, hipFree(*buf));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    hipError_t e = hipMalloc((void **)buf, need * sizeof(double));
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return fail(ctx, NB_ENOMEM, "hipMalloc of %zu bytes failed: %s", need * sizeof(double), hipGetErrorString(e));
+    }
+    *cap = need;
+    return NB_OK;
+}
+
+hipEvent_t take_event(nbody_ctx *ctx) {
+    if (!ctx->ev_free.empty()) {
+        hipEvent_t e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// Timed region helper: records an event pair around the enclosed launches.
+struct Timed {
+    nbody_ctx *ctx;
+    hipStream_t s;
+    int kind;
+    int64_t inter;
+    hipEvent_t a = nullptr;
+    Timed(nbody_ctx *c, hipStream_t st, int k, int64_t it) : ctx(c), s(st), kind(k), inter(it) {
+        if (ctx->prof && !capturing(s)) {
+            a = take_event(ctx);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(ctx);
+        if (!b) { ctx->ev_free.push_back(a); return; }
+        (void)hipEventRecord(b, s);
+        ctx->recs.push_back({a, b, kind, inter});
+    }
+};
+
+// Pair sum of targets [i0, i1) of one system; kick != 0 fuses the closing
+// half kick v += hdt a.
+nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64_t i0, int64_t i1,
+                      int mode, const nbody_plan &pl, int kick, double hdt, hipStream_t s) {
+    if (i1 <= i0) return NB_OK;
+    PairLaunch P{};
+    P.st = st;
+    P.sc = sc;
+    P.i0 = i0;
+    P.i1 = i1;
+    P.R = pl.R;
+    P.block = pl.block;
+    P.split = pl.split;
+    P.jsrc = pl.jsrc;
+    P.mode = mode;
+    P.kick = kick;
+    P.hdt = hdt;
+    if (!pair_config_supported(sc.prec, P.R, P.block, P.jsrc, mode))
+        return fail(ctx, NB_ENOTSUP, "unsupported plan R=%d block=%d jsrc=%d for mode %d", P.R, P.block, P.jsrc, mode);
+    if (P.split > 1) {
+        const size_t need = (size_t)P.split * 4 * (size_t)(i1 - i0);
+        nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, need);
+        if (r != NB_OK) return r;
+        P.part = ctx->part;
+    }
+    Timed t(ctx, s, 0, (i1 - i0) * sc.n);
+    hipError_t e = launch_pair(P, s);
+    if (e != hipSuccess) return hipfail(ctx, e, "pair-sum launch");
+    if (P.split > 1) {
+        e = launch_pair_reduce(P, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "pair-sum reduce launch");
+    }
+    return NB_OK;
+}
+
+nbody_status kdk_single(nbody_ctx *ctx, const State &st, const SysConst &sc, const nbody_plan &pl,
+                        double dt, hipStream_t s) {
+    const double h = 0.5 * dt;
+    const int fp32 = sc.prec == P_FP32;
+    {
+        Timed t(ctx, s, 1, 0);
+        hipError_t e = launch_kick_drift(st, sc.n, h, dt, fp32, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "kick-drift launch");
+    }
+    const int mode = st.phi ? MODE_ACC_PHI : MODE_ACC;
+    return run_pair(ctx, st, sc, 0, sc.n, mode, pl, 1, h, s);
+}
+
+nbody_plan mode_plan(nbody_ctx *ctx, int prec, int64_t n, int mode) {
+    if (mode == MODE_ACC) return plan_for(ctx, prec, n);
+    // the potential variants exist for one shape only: R = 1, 256 lanes, LDS
+    nbody_plan pl{1, 256, 1, 0};
+    const int64_t nblk = (n + 255) / 256;
+    while (nblk * pl.split < 2LL * ctx->cus && n / (2LL * pl.split) >= 512 && pl.split < 64) pl.split *= 2;
+    return pl;
+}
+
+void destroy_graphs(nbody_batch *b) {
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
+bool same_state(const State &a, const State &b) {
+    return a.x == b.x && a.y == b.y && a.z == b.z && a.m == b.m && a.vx == b.vx && a.vy == b.vy &&
+           a.vz == b.vz && a.ax == b.ax && a.ay == b.ay && a.az == b.az && a.phi == b.phi;
+}
+
+// Enqueue one leapfrog substep of width w * dt_sys for every system.
+nbody_status batch_substep(nbody_ctx *ctx, nbody_batch *b, const State &st, double w, hipStream_t s) {
+    hipError_t e = launch_kick_drift_batched(st, b->off_dev, b->sc_dev, b->B, b->ntot, w, s);
+    if (e != hipSuccess) return hipfail(ctx, e, "batched kick-drift launch");
+    for (int p = 0; p < 3; ++p) {
+        if (b->nitems[p] == 0) continue;
+        BatchLaunch L{};
+        L.st = st;
+        L.sys = b->sc_dev;
+        L.items = b->items[p];
+        L.nitems = b->nitems[p];
+        L.prec = p;
+        L.mode = MODE_ACC;
+        L.R = b->R;
+        L.block = b->block;
+        L.grid = b->grid[p];
+        L.kick_scale = w;
+        e = launch_pair_batched(L, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "batched pair-sum launch");
+    }
+    return NB_OK;
+}
+
+nbody_status batch_step_seq(nbody_ctx *ctx, nbody_batch *b, const State &st, int scheme, hipStream_t s) {
+    if (scheme == 0) return batch_substep(ctx, b, st, 1.0, s);
+    nbody_status r = batch_substep(ctx, b, st, kW1, s);
+    if (r == NB_OK) r = batch_substep(ctx, b, st, kW0, s);
+    if (r == NB_OK) r = batch_substep(ctx, b, st, kW1, s);
+    return r;
+}
+
+nbody_status batch_steps(nbody_ctx *ctx, nbody_batch *b, const nbody_sys *all, int64_t nsteps,
+                         int scheme, hipStream_t s) {
+    if (nsteps == 0 || b->ntot == 0) return NB_OK;
+    const State st = make_state(all);
+    if (!(b->flags & NB_BATCH_GRAPH) || capturing(s)) {
+        for (int64_t k = 0; k < nsteps; ++k) {
+            nbody_status r = batch_step_seq(ctx, b, st, scheme, s);
+            if (r != NB_OK) return r;
+        }
+        return NB_OK;
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : b->graphs)
+        if (g.scheme == scheme && same_state(g.st, st)) exec = g.exec;
+    if (!exec) {
+        if (!ctx->cap) HIPCHECK(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        HIPCHECK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        nbody_status r = batch_step_seq(ctx, b, st, scheme, ctx->cap);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+        if (r != NB_OK) { if (graph) (void)hipGraphDestroy(graph); return r; }
+        if (e != hipSuccess) return hipfail(ctx, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hipfail(ctx, e, "hipGraphInstantiate");
+        b->graphs.push_back({st, scheme, exec});
+    }
+    for (int64_t k = 0; k < nsteps; ++k) HIPCHECK(ctx, hipGraphLaunch(exec, s));
+    return NB_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
+
+const char *nbody_last_error(const nbody_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+nbody_status nbody_ctx_create(int device, nbody_ctx **out) {
+    if (!out) return NB_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return NB_EHIP;
+    if (device < 0 || device >= count) return NB_EINVAL;
+    nbody_ctx *ctx = new (std::nothrow) nbody_ctx();
+    if (!ctx) return NB_ENOMEM;
+    ctx->device = device;
+    DevGuard g(device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->cus = cus;
+    if (hipMalloc((void **)&ctx->sysc, sizeof(SysConst)) != hipSuccess) {
+        delete ctx;
+        return NB_ENOMEM;
+    }
+    *out = ctx;
+    return NB_OK;
+}
+
+nbody_status nbody_ctx_destroy(nbody_ctx *ctx) {
+    if (!ctx) return NB_OK;
+    DevGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &r : ctx->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+    if (ctx->part) (void)hipFree(ctx->part);
+    if (ctx->phi) (void)hipFree(ctx->phi);
+    if (ctx->sysc) (void)hipFree(ctx->sysc);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    delete ctx;
+    return NB_OK;
+}
+
+nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, false);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK || sys->n == 0) return r;
+        DevGuard g(ctx->device);
+        const int mode = sys->phi ? MODE_ACC_PHI : MODE_ACC;
+        const nbody_plan pl = mode_plan(ctx, prm->prec, sys->n, mode);
+        return run_pair(ctx, make_state(sys), make_sysconst(prm, 0, sys->n, 0.0), 0, sys->n, mode, pl, 0,
+                        0.0, (hipStream_t)stream);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_accel");
+    }
+}
+
+nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm, int64_t i0,
+                              int64_t i1, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, false);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK) return r;
+        if (i0 < 0 || i1 < i0 || i1 > sys->n)
+            return fail(ctx, NB_EINVAL, "row range [%lld, %lld) outside [0, %lld)", (long long)i0, (long long)i1,
+                        (long long)sys->n);
+        if (sys->n == 0 || i0 == i1) return NB_OK;
+        DevGuard g(ctx->device);
+        const int mode = sys->phi ? MODE_ACC_PHI : MODE_ACC;
+        const nbody_plan pl = mode_plan(ctx, prm->prec, sys->n, mode);
+        return run_pair(ctx, make_state(sys), make_sysconst(prm, 0, sys->n, 0.0), i0, i1, mode, pl, 0, 0.0,
+                        (hipStream_t)stream);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_rows");
+    }
+}
+
+static nbody_status step_common(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
+                                int64_t nsteps, void *stream, bool o4) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, true);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK) return r;
+        if (!is_finite(dt)) return fail(ctx, NB_EINVAL, "dt must be finite");
+        if (nsteps < 0) return fail(ctx, NB_EINVAL, "nsteps must be >= 0");
+        if (sys->n == 0 || nsteps == 0) return NB_OK;
+        DevGuard g(ctx->device);
+        const State st = make_state(sys);
+        const SysConst sc = make_sysconst(prm, 0, sys->n, dt);
+        const int mode = sys->phi ? MODE_ACC_PHI : MODE_ACC;
+        const nbody_plan pl = mode_plan(ctx, prm->prec, sys->n, mode);
+        hipStream_t s = (hipStream_t)stream;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            if (o4) {
+                r = kdk_single(ctx, st, sc, pl, kW1 * dt, s);
+                if (r == NB_OK) r = kdk_single(ctx, st, sc, pl, kW0 * dt, s);
+                if (r == NB_OK) r = kdk_single(ctx, st, sc, pl, kW1 * dt, s);
+            } else {
+                r = kdk_single(ctx, st, sc, pl, dt, s);
+            }
+            if (r != NB_OK) return r;
+        }
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in step");
+    }
+}
+
+nbody_status nbody_step_kdk(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt, int64_t nsteps,
+                            void *stream) {
+    return step_common(ctx, sys, prm, dt, nsteps, stream, false);
+}
+
+nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt, int64_t nsteps,
+                           void *stream) {
+    return step_common(ctx, sys, prm, dt, nsteps, stream, true);
+}
+
+nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm, nbody_diag_t *out_dev,
+                        void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, true);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK) return r;
+        if (!out_dev) return fail(ctx, NB_EINVAL, "out_dev is NULL");
+        DevGuard g(ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = sys->n;
+        r = ensure(ctx, &ctx->phi, &ctx->phi_cap, (size_t)std::max<int64_t>(n, 1));
+        if (r != NB_OK) return r;
+        State st = make_state(sys);
+        st.phi = ctx->phi;
+        nbody_params p64 = *prm;
+        p64.prec = NB_FP64;  // diagnostics are always float64
+        const SysConst sc = make_sysconst(&p64, 0, n, 0.0);
+        if (n > 0) {
+            const nbody_plan pl = mode_plan(ctx, NB_FP64, n, MODE_PHI);
+            r = run_pair(ctx, st, sc, 0, n, MODE_PHI, pl, 0, 0.0, s);
+            if (r != NB_OK) return r;
+        }
+        hipError_t e = launch_set_sysconst(ctx->sysc, sc, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "sysconst upload");
+        e = launch_diag_reduce(st, ctx->phi, ctx->sysc, 1, (double *)out_dev, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "diag reduce launch");
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_diag");
+    }
+}
+
+// ---- batched ---------------------------------------------------------------
+
+nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off, const nbody_params *prm,
+                                const double *dt, uint32_t flags, nbody_batch **out) {
+    if (!ctx) return NB_EINVAL;
+    if (!out) return fail(ctx, NB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (B < 1) return fail(ctx, NB_EINVAL, "B must be >= 1");
+    if (!off || !prm) return fail(ctx, NB_EINVAL, "off and prm must not be NULL");
+    if (off[0] != 0) return fail(ctx, NB_EINVAL, "off[0] must be 0");
+    for (int32_t b = 0; b < B; ++b) {
+        if (off[b + 1] < off[b]) return fail(ctx, NB_EINVAL, "offsets must be non-decreasing (system %d)", b);
+        if (off[b + 1] - off[b] > INT32_MAX) return fail(ctx, NB_EINVAL, "system %d has >= 2^31 particles", b);
+        nbody_status r = check_params(ctx, &prm[b]);
+        if (r != NB_OK) return fail(ctx, r, "system %d: %s", b, ctx->err.c_str());
+        if (dt && !is_finite(dt[b])) return fail(ctx, NB_EINVAL, "dt of system %d is not finite", b);
+    }
+    try {
+        DevGuard g(ctx->device);
+        nbody_batch *bt = new nbody_batch();
+        bt->B = B;
+        bt->flags = flags;
+        bt->off.assign(off, off + B + 1);
+        bt->ntot = off[B];
+        for (int32_t b = 0; b < B; ++b) {
+            bt->sc.push_back(make_sysconst(&prm[b], off[b], off[b + 1] - off[b], dt ? dt[b] : 0.0));
+            if (prm[b].prec == NB_FP32) bt->any_fp32 = 1;
+        }
+        auto cleanup = [&](nbody_status st, const char *what, hipError_t e) {
+            nbody_batch_destroy(ctx, bt);
+            return e != hipSuccess ? hipfail(ctx, e, what) : fail(ctx, st, "%s", what);
+        };
+        hipError_t e = hipMalloc((void **)&bt->off_dev, sizeof(int64_t) * (B + 1));
+        if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc offsets", e);
+        e = hipMalloc((void **)&bt->sc_dev, sizeof(SysConst) * B);
+        if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc system table", e);
+        e = hipMemcpy(bt->off_dev, bt->off.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(NB_EHIP, "copy offsets", e);
+        e = hipMemcpy(bt->sc_dev, bt->sc.data(), sizeof(SysConst) * B, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(NB_EHIP, "copy system table", e);
+        // work lists: tiles of block*R targets, largest systems first
+        const int64_t per = (int64_t)bt->block * bt->R;
+        std::vector<int32_t> order(B);
+        for (int32_t b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return bt->sc[a].n > bt->sc[c].n; });
+        std::vector<WorkItem> lists[3], all;
+        for (int32_t b : order) {
+            const SysConst &c = bt->sc[b];
+            for (int64_t i = c.off; i < c.off + c.n; i += per) {
+                lists[c.prec].push_back({b, 0, i});
+            }
+            for (int64_t i = c.off; i < c.off + c.n; i += 256) all.push_back({b, 0, i});
+        }
+        for (int p = 0; p < 3; ++p) {
+            bt->nitems[p] = (int32_t)lists[p].size();
+            if (lists[p].empty()) continue;
+            e = hipMalloc((void **)&bt->items[p], sizeof(WorkItem) * lists[p].size());
+            if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc work list", e);
+            e = hipMemcpy(bt->items[p], lists[p].data(), sizeof(WorkItem) * lists[p].size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return cleanup(NB_EHIP, "copy work list", e);
+        }
+        for (int p = 0; p < 3; ++p)
+            bt->grid[p] = std::min<int32_t>(bt->nitems[p], pair_batched_occupancy(p, bt->R, bt->block, MODE_ACC) * ctx->cus);
+        bt->nitems_all = (int32_t)all.size();
+        bt->grid_all = std::min<int32_t>(bt->nitems_all, pair_batched_occupancy(P_FP64, 1, 256, MODE_PHI) * ctx->cus);
+        if (!all.empty()) {
+            e = hipMalloc((void **)&bt->items_all, sizeof(WorkItem) * all.size());
+            if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc work list", e);
+            e = hipMemcpy(bt->items_all, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return cleanup(NB_EHIP, "copy work list", e);
+        }
+        *out = bt;
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_batch_create");
+    }
+}
+
+nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *b) {
+    if (!b) return NB_OK;
+    DevGuard g(ctx ? ctx->device : 0);
+    (void)hipDeviceSynchronize();
+    destroy_graphs(b);
+    for (int p = 0; p < 3; ++p)
+        if (b->items[p]) (void)hipFree(b->items[p]);
+    if (b->items_all) (void)hipFree(b->items_all);
+    if (b->off_dev) (void)hipFree(b->off_dev);
+    if (b->sc_dev) (void)hipFree(b->sc_dev);
+    delete b;
+    return NB_OK;
+}
+
+nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *b, nbody_plan *out) {
+    if (!ctx) return NB_EINVAL;
+    if (!b || !out) return fail(ctx, NB_EINVAL, "batch and out must not be NULL");
+    *out = nbody_plan{b->R, b->block, 1, 0};
+    return NB_OK;
+}
+
+static nbody_status check_batch_sys(nbody_ctx *ctx, const nbody_batch *b, const nbody_sys *all, bool need_v) {
+    if (!b) return fail(ctx, NB_EINVAL, "batch is NULL");
+    nbody_status r = check_sys(ctx, all, need_v);
+    if (r != NB_OK) return r;
+    if (all->n != b->ntot) return fail(ctx, NB_EINVAL, "all->n (%lld) != off[B] (%lld)", (long long)all->n, (long long)b->ntot);
+    return NB_OK;
+}
+
+nbody_status nbody_accel_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys *all, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_batch_sys(ctx, b, all, false);
+        if (r != NB_OK || b->ntot == 0) return r;
+        DevGuard g(ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        const State st = make_state(all);
+        for (int p = 0; p < 3; ++p) {
+            if (b->nitems[p] == 0) continue;
+            BatchLaunch L{};
+            L.st = st;
+            L.st.phi = nullptr;
+            L.sys = b->sc_dev;
+            L.items = b->items[p];
+            L.nitems = b->nitems[p];
+            L.prec = p;
+            L.mode = MODE_ACC;
+            L.R = b->R;
+            L.block = b->block;
+            L.grid = b->grid[p];
+            L.kick_scale = 0.0;
+            Timed t(ctx, s, 0, 0);
+            hipError_t e = launch_pair_batched(L, s);
+            if (e != hipSuccess) return hipfail(ctx, e, "batched pair-sum launch");
+        }
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_batched");
+    }
+}
+
+nbody_status nbody_step_kdk_batched(nbody_ctx *ctx, nbody_batch *b, nbody_sys *all, int64_t nsteps, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_batch_sys(ctx, b, all, true);
+        if (r != NB_OK) return r;
+        if (nsteps < 0) return fail(ctx, NB_EINVAL, "nsteps must be >= 0");
+        DevGuard g(ctx->device);
+        return batch_steps(ctx, b, all, nsteps, 0, (hipStream_t)stream);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_step_kdk_batched");
+    }
+}
+
+nbody_status nbody_step_o4_batched(nbody_ctx *ctx, nbody_batch *b, nbody_sys *all, int64_t nsteps, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_batch_sys(ctx, b, all, true);
+        if (r != NB_OK) return r;
+        if (nsteps < 0) return fail(ctx, NB_EINVAL, "nsteps must be >= 0");
+        DevGuard g(ctx->device);
+        return batch_steps(ctx, b, all, nsteps, 1, (hipStream_t)stream);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_step_o4_batched");
+    }
+}
+
+nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys *all, nbody_diag_t *out_dev,
+                                void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_batch_sys(ctx, b, all, true);
+        if (r != NB_OK) return r;
+        if (!out_dev) return fail(ctx, NB_EINVAL, "out_dev is NULL");
+        DevGuard g(ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        r = ensure(ctx, &ctx->phi, &ctx->phi_cap, (size_t)std::max<int64_t>(b->ntot, 1));
+        if (r != NB_OK) return r;
+        State st = make_state(all);
+        st.phi = ctx->phi;
+        if (b->nitems_all > 0) {
+            BatchLaunch L{};
+            L.st = st;
+            L.sys = b->sc_dev;
+            L.items = b->items_all;
+            L.nitems = b->nitems_all;
+            L.prec = P_FP64;
+            L.mode = MODE_PHI;
+            L.R = 1;
+            L.block = 256;
+            L.grid = b->grid_all;
+            L.kick_scale = 0.0;
+            hipError_t e = launch_pair_batched(L, s);
+            if (e != hipSuccess) return hipfail(ctx, e, "batched potential launch");
+        }
+        hipError_t e = launch_diag_reduce(st, ctx->phi, b->sc_dev, b->B, (double *)out_dev, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "batched diag launch");
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_diag_batched");
+    }
+}
+
+// ---- plans -------------------------------------------------------------------
+
+nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, nbody_plan *out) {
+    if (!ctx) return NB_EINVAL;
+    if (!out) return fail(ctx, NB_EINVAL, "out is NULL");
+    if (prec < 0 || prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", prec);
+    if (n < 0) return fail(ctx, NB_EINVAL, "n must be >= 0");
+    *out = plan_for(ctx, prec, n);
+    return NB_OK;
+}
+
+nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, const nbody_plan *p) {
+    if (!ctx) return NB_EINVAL;
+    if (prec < 0 || prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", prec);
+    if (n < 0) return fail(ctx, NB_EINVAL, "n must be >= 0");
+    if (!p) {
+        ctx->plans.erase({prec, ilog2_ceil(n)});
+        return NB_OK;
+    }
+    if (p->split < 1 || p->split > 1024 || !pair_config_supported(prec, p->R, p->block, p->jsrc, MODE_ACC))
+        return fail(ctx, NB_EINVAL, "unsupported plan R=%d block=%d split=%d jsrc=%d", p->R, p->block, p->split, p->jsrc);
+    ctx->plans[{prec, ilog2_ceil(n)}] = *p;
+    return NB_OK;
+}
+
+nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms, nbody_plan *out) {
+    if (!ctx) return NB_EINVAL;
+    if (prec < 0 || prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", prec);
+    if (n < 1 || n > INT32_MAX) return fail(ctx, NB_EINVAL, "n must be in [1, 2^31)");
+    if (!is_finite(budget_ms)) return fail(ctx, NB_EINVAL, "budget_ms must be finite");
+    try {
+        DevGuard g(ctx->device);
+        // synthetic particles: a uniform cube, equal masses, in one scratch block
+        double *buf = nullptr;
+        HIPCHECK(ctx, hipMalloc((void **)&buf, sizeof(double) * 7 * (size_t)n));
+        std::vector<double> h(7 * (size_t)n);
+        uint64_t s = 0x9E3779B97F4A7C15ULL;
+        for (size_t i = 0; i < 3 * (size_t)n; ++i) {
+            s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+            h[i] = (double)(s >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        for (int64_t i = 0; i < n; ++i) h[3 * n + i] = 1.0 / (double)n;
+        hipError_t e = hipMemcpy(buf, h.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipFree(buf); return hipfail(ctx, e, "autotune upload"); }
+        State st{};
+        st.x = buf; st.y = buf + n; st.z = buf + 2 * n; st.m = buf + 3 * n;
+        st.ax = buf + 4 * n; st.ay = buf + 5 * n; st.az = buf + 6 * n;
+        nbody_params p{1.0, 0.01, prec, 0, 0.0, 0.0};
+        SysConst sc = make_sysconst(&p, 0, n, 0.0);
+        // long source sweeps behave alike, so large systems are timed
+        // against a prefix of the sources with the full target grid
+        const int64_t nsrc = std::min<int64_t>(n, 32768);
+        sc.n = nsrc;
+        std::vector<nbody_plan> cand;
+        const nbody_plan base = heuristic_plan(ctx, prec, n);
+        cand.push_back(base);
+        for (int jsrc = 0; jsrc <= 1; ++jsrc)
+            for (int block : {256, 128})
+                for (int R : {1, 2, 4})
+                    for (int split = 1; split <= 64; split *= 2) {
+                        const int64_t nblk = (n + (int64_t)block * R - 1) / ((int64_t)block * R);
+                        if (split > 1 && (nblk * split > 16LL * ctx->cus || n / split < 2LL * block)) continue;
+                        nbody_plan c{R, block, split, jsrc};
+                        if (c.R == base.R && c.block == base.block && c.split == base.split && c.jsrc == base.jsrc) continue;
+                        cand.push_back(c);
+                    }
+        hipEvent_t a, bev;
+        HIPCHECK(ctx, hipEventCreate(&a));
+        HIPCHECK(ctx, hipEventCreate(&bev));
+        const bool prof = ctx->prof;
+        ctx->prof = false;
+        double spent = 0.0, best_rate = -1.0;
+        nbody_plan best = base;
+        nbody_status result = NB_OK;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            if (c > 0 && budget_ms > 0 && spent >= budget_ms) break;
+            const nbody_plan &pl = cand[c];
+            // sources are [0, nsrc): scale the split for the true n
+            nbody_plan run = pl;
+            float ms = 0.0f;
+            result = run_pair(ctx, st, sc, 0, n, MODE_ACC, run, 0, 0.0, nullptr);  // warm-up
+            if (result != NB_OK) break;
+            (void)hipEventRecord(a, nullptr);
+            const int reps = 2;
+            for (int k = 0; k < reps && result == NB_OK; ++k)
+                result = run_pair(ctx, st, sc, 0, n, MODE_ACC, run, 0, 0.0, nullptr);
+            (void)hipEventRecord(bev, nullptr);
+            if (result != NB_OK) break;
+            e = hipEventSynchronize(bev);
+            if (e != hipSuccess) { result = hipfail(ctx, e, "autotune sync"); break; }
+            (void)hipEventElapsedTime(&ms, a, bev);
+            spent += ms * 1.5;
+            const double rate = (double)n * (double)nsrc * reps / (ms * 1e-3);
+            if (rate > best_rate) { best_rate = rate; best = pl; }
+        }
+        ctx->prof = prof;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(bev);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(buf);
+        if (result != NB_OK) return result;
+        ctx->plans[{prec, ilog2_ceil(n)}] = best;
+        if (out) *out = best;
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_autotune");
+    }
+}
+
+// ---- profiling ------------------------------------------------------------------
+
+nbody_status nbody_profile_enable(nbody_ctx *ctx, int on) {
+    if (!ctx) return NB_EINVAL;
+    ctx->prof = on != 0;
+    return NB_OK;
+}
+
+nbody_status nbody_profile_read(nbody_ctx *ctx, nbody_profile_t *out) {
+    if (!ctx) return NB_EINVAL;
+    if (!out) return fail(ctx, NB_EINVAL, "out is NULL");
+    DevGuard g(ctx->device);
+    nbody_profile_t p{};
+    for (auto &r : ctx->recs) {
+        HIPCHECK(ctx, hipEventSynchronize(r.b));
+        float ms = 0.0f;
+        HIPCHECK(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.kind == 0) { p.accel_launches++; p.accel_ms += ms; p.interactions += r.inter; }
+        else { p.update_launches++; p.update_ms += ms; }
+        ctx->ev_free.push_back(r.a);
+        ctx->ev_free.push_back(r.b);
+    }
+    ctx->recs.clear();
+    *out = p;
+    return NB_OK;
+}
+
+}  // extern "C"

@@ -22,3 +22,20 @@ def orc():
     elif not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def nb():
+    """The ctypes binding of libnbody.so (fails loudly if it is not built)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_1803_01190_amd import nbody
+    return nbody
+
+
+@pytest.fixture(scope="session")
+def ctx(nb):
+    c = nb.Context(0)
+    yield c.h
+    c.close()

@@ -1,0 +1,184 @@
+"""GPU pair sum (Eqs. (1)-(2)) against the CPU oracle, through the C ABI.
+
+Float64 gate: eps_rms <= 1e-12 and eps_cond <= 1e-12 at every size and
+launch plan (see oracle.metrics for the definitions).  Mixed and float32
+gates are derived in the design doc from the arithmetic of those paths.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle.metrics import force_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# mixed: per-pair float32 terms (~10 u) summed over <= 256-source tiles in
+# float32 (<= 255 u of the tile's sum of |f|), tiles added in float64
+MIXED_TOL = {"eps_cond": 2e-5, "eps_rms": 2e-5}
+# float32 (the paper's SP): float32 positions and a float32 running sum over
+# all N sources; bound ~ (N + 8 |r|/|dr|) u, checked loosely
+FP32_TOL = {"eps_cond": 1e-3}
+
+
+def run_accel(nb, ctx, ic, eps, prec, halo=None, plan=None, phi=False, G=1.0):
+    s = nb.System.from_arrays(ic, with_phi=phi)
+    prm = nb.Params(G=G, eps=eps, prec=prec)
+    if halo is not None:
+        prm.halo, prm.halo_v2, prm.halo_rc = True, halo.v2, halo.rc
+    if plan is not None:
+        nb.nbody_plan_set(ctx, prec, s.n, plan)
+    try:
+        nb.nbody_accel(ctx, s, prm)
+        torch.cuda.synchronize()
+    finally:
+        if plan is not None:  # back to the heuristic plan for this size class
+            nb.nbody_plan_set(ctx, prec, s.n, None)
+    return s.numpy()
+
+
+def oracle_accel(orc, ic, eps, halo=None, G=1.0):
+    ax, ay, az, phi, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], G, eps, want_phi=True, want_scale=True)
+    if halo is not None:
+        hx, hy, hz = orc.halo_accel(ic["x"], ic["y"], ic["z"], orc.Halo(halo.v2, halo.rc))
+        ax, ay, az = ax + hx, ay + hy, az + hz
+        A = A + np.sqrt(hx * hx + hy * hy + hz * hz)
+    return np.stack([ax, ay, az]), phi, A
+
+
+def errs(got, ref, A):
+    return force_errors(np.stack([got["ax"], got["ay"], got["az"]]), ref, A)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 257, 1021, 4096, 4099])
+def test_fp64_sizes(nb, ctx, orc, n):
+    print(f"[case] fp64 plummer n={n}", flush=True)
+    ic = wl.plummer(n, 100 + n)
+    ref, _, A = oracle_accel(orc, ic, 0.01)
+    got = run_accel(nb, ctx, ic, 0.01, nb.NB_FP64)
+    if n == 1:
+        assert got["ax"][0] == 0 and got["ay"][0] == 0 and got["az"][0] == 0
+        return
+    e = errs(got, ref, A)
+    assert e["eps_rms"] <= FP64_TOL and e["eps_cond"] <= FP64_TOL, e
+
+
+PLANS = [dict(R=R, block=b, split=s, jsrc=j) for j in (0, 1) for b in (128, 256) for R in (1, 2, 4)
+         for s in (1, 3, 8)]
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: f"R{p['R']}b{p['block']}s{p['split']}j{p['jsrc']}")
+def test_fp64_every_plan(nb, ctx, orc, plan):
+    # a ragged size that spans several tiles in every plan
+    n = 2 * 1024 + 37
+    print(f"[case] fp64 plan {plan} n={n}", flush=True)
+    ic = wl.exp_disk(n, 7)
+    halo = wl.default_halo()
+    ref, _, A = oracle_accel(orc, ic, 0.02, halo)
+    got = run_accel(nb, ctx, ic, 0.02, nb.NB_FP64, halo=halo, plan=plan)
+    e = errs(got, ref, A)
+    assert e["eps_rms"] <= FP64_TOL and e["eps_cond"] <= FP64_TOL, e
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+@pytest.mark.parametrize("jsrc", [0, 1])
+def test_reduced_precision(nb, ctx, orc, prec, jsrc):
+    n = 4099
+    print(f"[case] {prec} jsrc={jsrc} n={n}", flush=True)
+    ic = wl.plummer(n, 5)
+    ref, _, A = oracle_accel(orc, ic, 0.01)
+    got = run_accel(nb, ctx, ic, 0.01, nb.PREC[prec], plan=dict(R=2, block=256, split=1, jsrc=jsrc))
+    e = errs(got, ref, A)
+    tol = MIXED_TOL if prec == "mixed" else FP32_TOL
+    for k, v in tol.items():
+        assert e[k] <= v, (prec, e)
+    if prec == "mixed":
+        # float64 differences before rounding: far better than float32
+        e32 = errs(run_accel(nb, ctx, ic, 0.01, nb.NB_FP32), ref, A)
+        assert e["eps_rms"] < e32["eps_rms"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_potential(nb, ctx, orc, prec):
+    n = 1500
+    print(f"[case] potential {prec} n={n}", flush=True)
+    ic = wl.plummer(n, 9)
+    ref, phi_ref, A = oracle_accel(orc, ic, 0.01)
+    got = run_accel(nb, ctx, ic, 0.01, nb.PREC[prec], phi=True)
+    rel = np.max(np.abs(got["phi"] - phi_ref) / np.abs(phi_ref))
+    assert rel <= {"fp64": 1e-13, "mixed": 2e-5, "fp32": 1e-3}[prec], rel
+    e = errs(got, ref, A)
+    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_zero_softening_coincident(nb, ctx, orc, prec):
+    # eps = 0 with coincident particles: their mutual term is defined as zero
+    print(f"[case] eps=0 coincident {prec}", flush=True)
+    ic = wl.plummer(300, 11)
+    for k in ("x", "y", "z"):
+        ic[k][5] = ic[k][6]
+        ic[k][100] = ic[k][101] = ic[k][102]
+    ref, _, A = oracle_accel(orc, ic, 0.0)
+    got = run_accel(nb, ctx, ic, 0.0, nb.PREC[prec])
+    assert all(np.all(np.isfinite(got[k])) for k in ("ax", "ay", "az"))
+    e = errs(got, ref, A)
+    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec], e
+
+
+def test_rows_bitwise(nb, ctx):
+    # one GPU's share of a target split: rows [i0, i1) equal the full launch
+    n = 5000
+    ic = wl.plummer(n, 12)
+    prm = nb.Params(eps=0.01, prec=nb.NB_FP64)
+    full = nb.System.from_arrays(ic)
+    nb.nbody_accel(ctx, full, prm)
+    part = nb.System.from_arrays(ic)
+    for t in ("ax", "ay", "az"):
+        part[t].fill_(7.0)
+    nb.nbody_accel_rows(ctx, part, prm, 1234, 3777)
+    torch.cuda.synchronize()
+    for t in ("ax", "ay", "az"):
+        assert torch.equal(part[t][1234:3777], full[t][1234:3777])
+        assert torch.all(part[t][:1234] == 7.0) and torch.all(part[t][3777:] == 7.0)
+
+
+def test_deterministic(nb, ctx):
+    ic = wl.exp_disk(3000, 13)
+    for prec in (nb.NB_FP64, nb.NB_MIXED, nb.NB_FP32):
+        a = run_accel(nb, ctx, ic, 0.02, prec)
+        b = run_accel(nb, ctx, ic, 0.02, prec)
+        for k in ("ax", "ay", "az"):
+            assert np.array_equal(a[k], b[k])
+
+
+def test_translation_mixed(nb, ctx, orc):
+    # mixed forms separations in float64, so a far offset costs nothing
+    ic = wl.plummer(2000, 14)
+    ref, _, A = oracle_accel(orc, ic, 0.01)
+    sh = dict(ic)
+    sh["x"] = ic["x"] + 1000.0
+    got = run_accel(nb, ctx, sh, 0.01, nb.NB_MIXED)
+    e = errs(got, ref, A)
+    assert e["eps_cond"] <= 2e-5, e
+
+
+def test_empty_and_validation(nb, ctx):
+    prm = nb.Params(eps=0.01)
+    s0 = nb.System(0)
+    nb.nbody_accel(ctx, s0, prm)  # n = 0 is a no-op
+    s = nb.System.from_arrays(wl.plummer(10, 1))
+    for bad in (nb.Params(eps=-1.0), nb.Params(eps=float("nan")), nb.Params(G=float("inf")),
+                nb.Params(prec=7), nb.Params(halo=True, halo_v2=-1.0, halo_rc=1.0)):
+        with pytest.raises(nb.NBodyError) as ei:
+            nb.nbody_accel(ctx, s, bad)
+        assert ei.value.status == nb.NB_EINVAL
+    with pytest.raises(nb.NBodyError):
+        nb.nbody_step_kdk(ctx, s, prm, float("nan"), 1)
+    with pytest.raises(nb.NBodyError):
+        nb.nbody_step_kdk(ctx, s, prm, 1e-3, -1)
+    with pytest.raises(nb.NBodyError):
+        nb.nbody_accel_rows(ctx, s, prm, 5, 11)
+    with pytest.raises(nb.NBodyError):
+        nb.nbody_plan_set(ctx, nb.NB_FP64, 10, {"R": 3, "block": 256, "split": 1})
