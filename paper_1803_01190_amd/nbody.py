@@ -275,6 +275,29 @@ def nbody_plan_set(ctx, prec: int, n: int, plan: dict | None):
     _check(ctx, _lib.nbody_plan_set(ctx, int(prec), int(n), ctypes.byref(p)))
 
 
+TUNED_PLANS = os.path.join(_HERE, "tuned_plans.json")
+
+
+def read_plans(path: str = TUNED_PLANS, arch: str = "gfx950") -> dict:
+    """{prec_name: {log2n: plan}} from a plan-cache file (empty if absent)."""
+    import json
+    try:
+        with open(path) as f:
+            return json.load(f).get(arch, {})
+    except (OSError, ValueError):
+        return {}
+
+
+def load_plans(ctx, path: str = TUNED_PLANS, arch: str = "gfx950") -> int:
+    """Pin every plan of a plan-cache file; returns how many were pinned."""
+    k = 0
+    for prec, table in read_plans(path, arch).items():
+        for log2n, plan in table.items():
+            nbody_plan_set(ctx, PREC[prec], 1 << int(log2n), plan)
+            k += 1
+    return k
+
+
 def nbody_autotune(ctx, prec: int, n: int, budget_ms: float = 2000.0) -> dict:
     p = c_plan()
     _check(ctx, _lib.nbody_autotune(ctx, int(prec), int(n), float(budget_ms), ctypes.byref(p)))
