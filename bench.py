@@ -84,6 +84,11 @@ def main():
                          "tuned_plans.json when it has this size, else autotune")
     ap.add_argument("--retune", action="store_true", help="autotune even if a cached plan exists")
     ap.add_argument("--plans-out", default=None, help="write the plans used in plan-cache form")
+    ap.add_argument("--workload", default="disk", choices=["disk", "batched", "serving"],
+                    help="disk: the headline N=2^20 step (default); batched: 256 independent systems "
+                         "in one persistent launch vs one launch per system; serving: Poisson "
+                         "request stream through the continuous-batching loop")
+    ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
     ap.add_argument("--profile-run", action="store_true",
                     help="run for counter collection: no CPU baseline, plus a copy kernel of "
                          "known size to calibrate FETCH_SIZE / WRITE_SIZE")
@@ -101,6 +106,10 @@ def main():
     from paper_1803_01190_amd import nbody as nb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     dev = torch.device("cuda:0")
     n, dt, eps = args.n, 1e-3, 0.02
     halo = wl.default_halo()
@@ -256,6 +265,124 @@ def main():
                           for k, v in results.items()},
     }
     print(json.dumps(out))
+    ctx.close()
+
+
+def bench_batched(args):
+    """256 independent systems (half Plummer, half disk), N log-uniform in
+    [2^10, 2^16], mixed precision, KDK: one persistent launch per step replayed
+    from a HIP graph, against one launch per system per step."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1803_01190_amd import nbody as nb
+
+    B, steps = 256, args.steps if args.steps != 10 else 100
+    mix = wl.batch_mix(B, 4)
+    off = mix["off"]
+    sizes = np.diff(off)
+    inter = float(np.sum(sizes.astype(np.float64) ** 2))
+    h = wl.default_halo()
+    prms = [nb.Params(eps=0.01 if mix["kind"][k] == "plummer" else 0.02, prec=nb.NB_MIXED,
+                      halo=mix["kind"][k] == "disk", halo_v2=h.v2, halo_rc=h.rc) for k in range(B)]
+    ctx = nb.Context(0)
+    out = {}
+    # persistent + graph
+    b = nb.nbody_batch_create(ctx.h, off, prms, [1e-3] * B, flags=nb.NB_BATCH_GRAPH)
+    s = nb.System.from_arrays(mix)
+    nb.nbody_accel_batched(ctx.h, b, s)
+    nb.nbody_step_kdk_batched(ctx.h, b, s, 1)  # capture + warm-up
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    w0 = time.perf_counter()
+    evs[0].record()
+    for k in range(steps):
+        nb.nbody_step_kdk_batched(ctx.h, b, s, 1)
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    lat = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+    out["persistent_graph"] = {"value": steps * inter / wall, "ms_per_step": 1e3 * wall / steps,
+                               "latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)}}
+    nb.nbody_batch_destroy(ctx.h, b)
+    log(f"[bench] batched persistent+graph: {out['persistent_graph']}")
+    # one launch per system (same plan as the batch: R=1, block=256, split=1)
+    systems = [nb.System.from_arrays({f: mix[f][off[k]:off[k + 1]] for f in wl.FIELDS}) for k in range(B)]
+    for k in range(B):
+        nb.nbody_plan_set(ctx.h, nb.NB_MIXED, int(sizes[k]), {"R": 1, "block": 256, "split": 1, "jsrc": 0})
+        nb.nbody_accel(ctx.h, systems[k], prms[k])
+    ps = max(1, steps // 10)
+    for k in range(B):
+        nb.nbody_step_kdk(ctx.h, systems[k], prms[k], 1e-3, 1)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(ps):
+        for k in range(B):
+            nb.nbody_step_kdk(ctx.h, systems[k], prms[k], 1e-3, 1)
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter() - w0
+    out["one_launch_per_system"] = {"value": ps * inter / wall1, "ms_per_step": 1e3 * wall1 / ps, "steps": ps}
+    log(f"[bench] one launch per system: {out['one_launch_per_system']}")
+    res = {"metric": "batched pair-interactions/s (256 systems, N log-uniform 2^10..2^16, mixed)",
+           "value": out["persistent_graph"]["value"], "unit": "pair-interactions/s", "n_gpus": 1,
+           "steps": steps, "warmup": 1, "ms_per_step": out["persistent_graph"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE["mixed"],
+           "data": "synthetic",
+           "config": {"workload": "256 systems (128 Plummer, 128 disk), N_k log-uniform in [2^10, 2^16], "
+                                  "seed 4, KDK dt=1e-3", "sum_n": int(off[-1]), "sum_n2": inter},
+           "latency_ms": out["persistent_graph"]["latency_ms"], "modes": out,
+           "speedup_vs_per_system": out["persistent_graph"]["value"] / out["one_launch_per_system"]["value"]}
+    print(json.dumps(res))
+    ctx.close()
+
+
+def bench_serving(args):
+    """Poisson request stream through the continuous-batching loop.  Request
+    sizes are capped for a run of minutes: N log-uniform in [2^12, 2^16],
+    steps uniform in [10, 100], Plummer or disk, mixed with 10% FP64."""
+    import torch
+
+    import workloads as wl
+    from paper_1803_01190_amd import nbody as nb
+    from paper_1803_01190_amd.serving import GpuBackend, Request, Scheduler
+
+    ctx = nb.Context(0)
+    nreq = args.requests
+
+    def make(rate, seed):
+        rs = wl.request_stream(nreq, seed=seed, rate=rate, lo_log2=12, hi_log2=16, steps_lo=10, steps_hi=100,
+                               fp64_fraction=0.1)
+        return [Request(id=r["id"], t_arrive=r["t_arrive"], n=r["n"], steps=r["steps"], model=r["model"],
+                        fp64=r["fp64"], seed=r["seed"]) for r in rs]
+
+    budget = 64 << 30
+    # capacity: everything arrives at once
+    be = GpuBackend(ctx.h, keep_state=False)
+    cap = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(1e9, 5)).summary()
+    be.close()
+    mu = cap["requests_per_s"]
+    log(f"[bench] serving capacity {mu:.2f} req/s ({cap})")
+    sweep = []
+    for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
+        be = GpuBackend(ctx.h, keep_state=False)
+        smry = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(frac * mu, 5)).summary()
+        be.close()
+        smry["rate_req_per_s"] = frac * mu
+        smry["rate_frac"] = frac
+        sweep.append(smry)
+        log(f"[bench] serving rate {frac:.2f} mu: {smry}")
+    torch.cuda.synchronize()
+    mid = sweep[2]
+    res = {"metric": "serving throughput (requests/s, pair-interactions/s) and p50/p99 latency",
+           "value": mid["interactions_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,
+           "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": DTYPE["mixed"], "data": "synthetic",
+           "config": {"workload": f"{nreq} Poisson-arriving requests per rate, N log-uniform in [2^12, 2^16], "
+                                  "steps uniform in [10, 100], Plummer or disk, 10% FP64, HBM budget 64 GiB",
+                      "capacity_req_per_s": mu},
+           "latency_s": mid["latency_s"], "capacity": cap, "sweep": sweep}
+    print(json.dumps(res))
     ctx.close()
 
 

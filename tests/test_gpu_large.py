@@ -1,0 +1,88 @@
+"""Full-size parity: the N = 2^20 exponential disk (eps = 0.02, halo) in the
+launch configuration the benchmark times (plans from tuned_plans.json),
+checked on rows the oracle computes one by one (each summed over all N
+sources), plus the N = 2^17 disk with both integrators.
+
+Stated errors (frozen before timing, measured on 8192 rows of this
+workload): mixed eps_rms 1.8e-8 / eps_cond 1.6e-8, gated at 5e-8; fp32
+eps_rms 4.9e-4 / eps_cond 7.7e-4, gated at 2e-3; fp64 gated at 1e-12.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle.metrics import force_errors
+
+pytestmark = pytest.mark.gpu
+
+GATE = {"fp64": 1e-12, "mixed": 5e-8, "fp32": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def disk20():
+    return wl.exp_disk(1 << 20, 2)
+
+
+def oracle_rows(orc, ic, rows, eps, halo):
+    ax, ay, az, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], 1.0, eps, rows=rows, want_scale=True)
+    hx, hy, hz = orc.halo_accel(ic["x"][rows], ic["y"][rows], ic["z"][rows], orc.Halo(halo.v2, halo.rc))
+    return np.stack([ax + hx, ay + hy, az + hz]), A + np.sqrt(hx * hx + hy * hy + hz * hz)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_disk_2p20_sampled(nb, ctx, orc, disk20, prec):
+    n = 1 << 20
+    print(f"[case] disk 2^20 {prec} sampled rows", flush=True)
+    h = wl.default_halo()
+    nb.load_plans(ctx)
+    prm = nb.Params(eps=0.02, prec=nb.PREC[prec], halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    s = nb.System.from_arrays(disk20)
+    nb.nbody_accel(ctx, s, prm)
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(n, size=512, replace=False))
+    rt = torch.as_tensor(rows, device="cuda")
+    got = torch.stack([s["ax"][rt], s["ay"][rt], s["az"][rt]]).cpu().numpy()
+    ref, A = oracle_rows(orc, disk20, rows, 0.02, h)
+    e = force_errors(got, ref, A)
+    assert e["eps_rms"] <= GATE[prec] and e["eps_cond"] <= GATE[prec], (prec, e)
+    # one KDK step in the timed configuration: the sampled positions follow
+    # r + dt (v + dt/2 a) with the oracle's a
+    dt = 1e-3
+    nb.nbody_step_kdk(ctx, s, prm, dt, 1)
+    x1 = s["x"][rt].cpu().numpy()
+    want = disk20["x"][rows] + dt * (disk20["vx"][rows] + 0.5 * dt * ref[0])
+    # float64 state: rounding of r plus dt^2/2 times the force error of the path
+    tol = {"fp64": 1e-15, "mixed": 1e-13, "fp32": 1e-6}[prec]
+    assert np.max(np.abs(x1 - want)) <= tol * np.max(np.abs(want)), prec
+    # Newton's third law at full size: sum m a over all particles, without
+    # the halo, is round-off of sum m A
+    if prec == "fp64":
+        prm0 = nb.Params(eps=0.02, prec=nb.NB_FP64)
+        s2 = nb.System.from_arrays(disk20)
+        nb.nbody_accel(ctx, s2, prm0)
+        m = s2["m"]
+        net = torch.stack([(m * s2[k]).sum() for k in ("ax", "ay", "az")]).abs().max().item()
+        scale = float(np.sum(disk20["m"][rows] * A) * n / rows.size)
+        assert net <= 1e-13 * scale, (net, scale)
+
+
+@pytest.mark.parametrize("scheme", ["kdk", "o4"])
+def test_disk_2p17_integrators_conserve(nb, ctx, scheme):
+    # N = 2^17 disk: second- vs fourth-order.  L_z is conserved by both
+    # schemes up to round-off in float64; energy drift follows the order.
+    n = 1 << 17
+    print(f"[case] disk 2^17 {scheme} fp64", flush=True)
+    ic = wl.exp_disk(n, 3)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.NB_FP64, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    s = nb.System.from_arrays(ic)
+    nb.nbody_accel(ctx, s, prm)
+    d0 = nb.diag_dict(nb.nbody_diag(ctx, s, prm))
+    if scheme == "kdk":
+        nb.nbody_step_kdk(ctx, s, prm, 1e-3, 20)
+    else:
+        nb.nbody_step_o4(ctx, s, prm, 1e-3, 20)
+    d1 = nb.diag_dict(nb.nbody_diag(ctx, s, prm))
+    assert abs(d1["Lz"] - d0["Lz"]) <= 1e-13 * abs(d0["Lz"])
+    assert abs(d1["E"] - d0["E"]) <= 1e-6 * abs(d0["E"])
