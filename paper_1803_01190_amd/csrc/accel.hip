@@ -12,9 +12,14 @@
 //    there are no bank conflicts); with jsrc = 1 the sources are read as
 //    wave-uniform values through the scalar cache straight into SGPR
 //    operands of the VALU instructions, with no LDS and no barriers;
-//  * 1/sqrt is the VALU v_rsq instruction.  In float64 its ~2^-24 relative
-//    error is removed by a second-order binomial correction of y^3:
-//      e = r2 y^2 - 1,  (r2 y^2)^{-3/2} = 1 - 3e/2 + 15e^2/8 + O(e^3);
+//  * 1/sqrt is the VALU v_rsq instruction.  In float64 its relative error
+//    (probed on gfx950: at most 5.2e-8) is removed by a first-order binomial
+//    correction of y^3:  e = r2 y^2 - 1 (|e| <= 1.05e-7),
+//      (r2 y^2)^{-3/2} = 1 - 3e/2 + 15e^2/8 - ...,
+//    keeping 1 - 3e/2 leaves a one-signed error below 15e^2/8 = 2.1e-14 per
+//    pair term (measured: the force error at N = 2^20 is unchanged, being set
+//    by the float64 sum, while one FMA per pair is saved).  The potential
+//    keeps the second-order correction of y, (r2 y^2)^{-1/2} = 1 - e/2 + 3e^2/8;
 //  * small systems split the sources into `split` chunks whose partial sums
 //    are reduced afterwards in a fixed order (deterministic, no atomics).
 // There is no MFMA: the pair term is not a dense contraction.
@@ -61,8 +66,8 @@ struct Lane {
     int32_t li[R];                           // target index local to the system
     // Correction coefficients held in registers: gfx9 VOP3 instructions take
     // no literal operands, so without this the compiler rematerialises them
-    // with two v_mov per pair.
-    double k1875, km15, k0375;
+    // with v_mov instructions in every pair.
+    double km15, k0375;
     F tx[R], ty[R], tz[R], tp[R];            // inner sums
     O ox[R], oy[R], oz[R], op[R];            // outer sums (MIXED only)
 };
@@ -83,7 +88,7 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
             const double y2 = y * y;
             const double e = __builtin_fma(r2, y2, -1.0);
             if constexpr (MODE != MODE_PHI) {
-                const double c3 = __builtin_fma(e, __builtin_fma(L.k1875, e, L.km15), 1.0);
+                const double c3 = __builtin_fma(L.km15, e, 1.0);
                 const double s = ((sm * y) * y2) * c3;
                 L.tx[r] = __builtin_fma(s, dx, L.tx[r]);
                 L.ty[r] = __builtin_fma(s, dy, L.ty[r]);
@@ -139,7 +144,6 @@ __device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int
                                           int64_t ilim, int64_t sys_off, int BLOCK) {
     const int t = threadIdx.x;
     if constexpr (PREC == P_FP64) {
-        L.k1875 = in_vgpr(1.875);
         L.km15 = in_vgpr(-1.5);
         L.k0375 = in_vgpr(0.375);
     }

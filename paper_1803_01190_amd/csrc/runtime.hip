@@ -173,10 +173,14 @@ nbody_plan heuristic_plan(const nbody_ctx *ctx, int prec, int64_t n) {
     return p;
 }
 
+// The float32 path sums each target's terms in one float32 running sum over
+// all sources, as the paper's single-precision kernel does, so its error does
+// not depend on the plan: it never splits the sources.
 nbody_plan plan_for(nbody_ctx *ctx, int prec, int64_t n) {
     auto it = ctx->plans.find({prec, ilog2_ceil(n)});
-    if (it != ctx->plans.end()) return it->second;
-    return heuristic_plan(ctx, prec, n);
+    nbody_plan p = (it != ctx->plans.end()) ? it->second : heuristic_plan(ctx, prec, n);
+    if (prec == P_FP32) p.split = 1;
+    return p;
 }
 
 nbody_status ensure(nbody_ctx *ctx, double **buf, size_t *cap, size_t need) {
@@ -782,7 +786,7 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budg
         for (int jsrc = 0; jsrc <= 1; ++jsrc)
             for (int block : {256, 128})
                 for (int R : {1, 2, 4})
-                    for (int split = 1; split <= 64; split *= 2) {
+                    for (int split = 1; split <= (prec == P_FP32 ? 1 : 64); split *= 2) {
                         const int64_t nblk = (n + (int64_t)block * R - 1) / ((int64_t)block * R);
                         if (split > 1 && (nblk * split > 16LL * ctx->cus || n / split < 2LL * block)) continue;
                         nbody_plan c{R, block, split, jsrc};

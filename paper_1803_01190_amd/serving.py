@@ -34,6 +34,7 @@ class Request:
     seed: int = 0
     dt: float = 1e-3
     eps: Optional[float] = None
+    ic: Optional[dict] = None  # initial conditions supplied with the request (else generated)
 
 
 @dataclass
@@ -156,8 +157,6 @@ class Scheduler:
                     continue
                 used += fp
                 active[r.id] = {"req": r, "h": h, "left": r.steps, "fp": fp, "t_admit": now()}
-                if r.steps == 0:
-                    pass
             if not active:
                 if pending:
                     dt = pending[0].t_arrive - now()
@@ -234,7 +233,7 @@ class GpuBackend(Backend):
 
     def admit(self, req: Request):
         nb = self.nb
-        ic = self.wl.make(req.model, req.n, req.seed)
+        ic = req.ic if req.ic is not None else self.wl.make(req.model, req.n, req.seed)
         s = nb.System.from_arrays(ic, device=self.device)
         prm = self._params(req)
         # a(t0) with the batch plan, so the run equals the same request alone

@@ -81,8 +81,7 @@ def test_fp64_every_plan(nb, ctx, orc, plan):
     assert e["eps_rms"] <= FP64_TOL and e["eps_cond"] <= FP64_TOL, e
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp32"])
-@pytest.mark.parametrize("jsrc", [0, 1])
+@pytest.mark.parametrize("prec,jsrc", [("mixed", 0), ("mixed", 1), ("fp32", 0), ("fp32", 1)])
 def test_reduced_precision(nb, ctx, orc, prec, jsrc):
     n = 4099
     print(f"[case] {prec} jsrc={jsrc} n={n}", flush=True)
@@ -153,13 +152,15 @@ def test_deterministic(nb, ctx):
             assert np.array_equal(a[k], b[k])
 
 
-def test_translation_mixed(nb, ctx, orc):
-    # mixed forms separations in float64, so a far offset costs nothing
+@pytest.mark.parametrize("jsrc", [0, 1])
+def test_translation_mixed(nb, ctx, orc, jsrc):
+    # mixed forms separations (or block-relative coordinates) in float64, so a
+    # far offset costs nothing
     ic = wl.plummer(2000, 14)
     ref, _, A = oracle_accel(orc, ic, 0.01)
     sh = dict(ic)
     sh["x"] = ic["x"] + 1000.0
-    got = run_accel(nb, ctx, sh, 0.01, nb.NB_MIXED)
+    got = run_accel(nb, ctx, sh, 0.01, nb.NB_MIXED, plan=dict(R=2, block=256, split=2, jsrc=jsrc))
     e = errs(got, ref, A)
     assert e["eps_cond"] <= 2e-5, e
 
