@@ -89,7 +89,7 @@ def main():
                          "in one persistent launch vs one launch per system; serving: Poisson "
                          "request stream through the continuous-batching loop")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
-    ap.add_argument("--no-graph", action="store_true", help="serving: eager launches instead of graph replay")
+    ap.add_argument("--graph", action="store_true", help="serving: replay steps from HIP graphs")
     ap.add_argument("--profile-run", action="store_true",
                     help="run for counter collection: no CPU baseline, plus a copy kernel of "
                          "known size to calibrate FETCH_SIZE / WRITE_SIZE")
@@ -397,7 +397,7 @@ def bench_integrators(args):
     ref, _, tref = run("fp64", "o4", 2000, 100)
     log(f"[bench] reference fp64 o4 dt=5e-4 done in {tref:.1f}s")
     runs = {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "fp32"):
         for scheme, steps in (("kdk", 1000), ("o4", 1000), ("o4", 334)):
             st, worst, busy = run(prec, scheme, steps, 50)
             dx = np.sqrt(((st["x"] - ref["x"]) ** 2 + (st["y"] - ref["y"]) ** 2 + (st["z"] - ref["z"]) ** 2))
@@ -441,16 +441,16 @@ def bench_serving(args):
                         fp64=r["fp64"], seed=r["seed"], ic=ics[k]) for k, r in enumerate(base)]
 
     budget = 64 << 30
-    graph = not args.no_graph
+    graph = args.graph
     # capacity: everything arrives at once
-    be = GpuBackend(ctx.h, keep_state=False, graph=graph)
+    be = GpuBackend(ctx.h, keep_state=False, graph=graph, diagnostics=False)
     cap = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(1e9)).summary()
     be.close()
     mu = cap["requests_per_s"]
     log(f"[bench] serving capacity {mu:.2f} req/s ({cap})")
     sweep = []
     for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
-        be = GpuBackend(ctx.h, keep_state=False, graph=graph)
+        be = GpuBackend(ctx.h, keep_state=False, graph=graph, diagnostics=False)
         smry = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(frac * mu)).summary()
         be.close()
         smry["rate_req_per_s"] = frac * mu

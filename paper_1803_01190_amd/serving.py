@@ -68,8 +68,22 @@ class Backend:
         """Advance every handle by nsteps; return {handle: error} for failures."""
         raise NotImplementedError
 
-    def finish(self, handle) -> Result:  # gather the result and free the slot
-        raise NotImplementedError
+    def finish(self, handle) -> Result:
+        nb, torch = self.nb, self.torch
+        e = self.live[handle]
+        req, s, prm = e["req"], e["sys"], e["prm"]
+        d = state = None
+        with torch.cuda.stream(self.stream):
+            dt = nb.nbody_diag(self.ctx, s, prm, stream=self.stream) if self.diagnostics else None
+            if self.diagnostics or self.keep_state:
+                self.stream.synchronize()
+                d = nb.diag_dict(dt) if dt is not None else None
+                state = s.numpy() if self.keep_state else None
+        res = Result(req.id, req.n, req.steps, "fp64" if req.fp64 else "mixed", req.t_arrive, state=state, diag=d)
+        if d is not None and not all(math.isfinite(v) for v in d.values()):
+            res.error = "non-finite state"
+        self._release(handle)
+        return res
 
     def drop(self, handle) -> None:  # free without a result (after a failure)
         raise NotImplementedError
@@ -201,9 +215,14 @@ class Scheduler:
 class GpuBackend(Backend):
     """Drives libnbody.so: active requests live packed back to back in one set
     of device arrays; the pack is rebuilt (device-to-device copies) whenever
-    the set of active requests changes, together with its batch plan."""
+    the set of active requests changes, together with its batch plan.  HIP
+    graph replay is off by default here: the set of active requests changes
+    every few steps, and each change would need a new capture."""
 
-    def __init__(self, ctx, device="cuda", graph: bool = True, keep_state: bool = True):
+    BATCH_PLAN = {"R": 1, "block": 256, "split": 1, "jsrc": 0}
+
+    def __init__(self, ctx, device="cuda", graph: bool = False, keep_state: bool = True,
+                 diagnostics: bool = True):
         import torch
 
         from . import nbody as nb
@@ -214,7 +233,13 @@ class GpuBackend(Backend):
         self.device = device
         self.graph = graph
         self.keep_state = keep_state
+        self.diagnostics = diagnostics
         self.halo = wl.default_halo()
+        # all device work of the loop goes to one non-blocking stream (default
+        # priority), so the library's blocking table uploads on the legacy
+        # stream do not wait for running steps
+        self.stream = torch.cuda.Stream()
+        self.retired: list = []           # batch plans freed later (freeing synchronises)
         self.live: Dict[int, dict] = {}   # handle -> {req, sys (own arrays or view), prm}
         self.order: List[int] = []        # handles in pack order
         self.pack = None                  # packed System
@@ -234,14 +259,17 @@ class GpuBackend(Backend):
     def admit(self, req: Request):
         nb = self.nb
         ic = req.ic if req.ic is not None else self.wl.make(req.model, req.n, req.seed)
-        s = nb.System.from_arrays(ic, device=self.device)
+        with self.torch.cuda.stream(self.stream):
+            s = nb.System.from_arrays(ic, device=self.device)
         prm = self._params(req)
-        # a(t0) with the batch plan, so the run equals the same request alone
-        b = nb.nbody_batch_create(self.ctx, [0, req.n], [prm], [req.dt])
+        # a(t0) under the plan every batch uses (R 1, 256 lanes, no split,
+        # LDS), which gives the same bits as the batched kernel; this avoids
+        # creating (and synchronously destroying) a one-system batch
+        nb.nbody_plan_set(self.ctx, prm.prec, req.n, self.BATCH_PLAN)
         try:
-            nb.nbody_accel_batched(self.ctx, b, s)
+            nb.nbody_accel(self.ctx, s, prm, stream=self.stream)
         finally:
-            nb.nbody_batch_destroy(self.ctx, b)
+            nb.nbody_plan_set(self.ctx, prm.prec, req.n, None)
         h = req.id
         self.live[h] = {"req": req, "sys": s, "prm": prm}
         self.dirty = True
@@ -254,11 +282,12 @@ class GpuBackend(Backend):
         off = [0]
         for n in ns:
             off.append(off[-1] + n)
-        pack = nb.System(off[-1], device=self.device)
-        for k, h in enumerate(self.order):
-            src = self.live[h]["sys"]
-            for f in nb.FIELDS:
-                pack.t[f][off[k]:off[k + 1]].copy_(src.t[f])
+        with torch.cuda.stream(self.stream):
+            pack = nb.System(off[-1], device=self.device)
+            for k, h in enumerate(self.order):
+                src = self.live[h]["sys"]
+                for f in nb.FIELDS:
+                    pack.t[f][off[k]:off[k + 1]].copy_(src.t[f])
         for k, h in enumerate(self.order):
             view = nb.System(0, device=self.device)
             view.n = ns[k]
@@ -266,17 +295,27 @@ class GpuBackend(Backend):
             view.t["phi"] = None
             self.live[h]["sys"] = view
         if self.batch is not None:
-            nb.nbody_batch_destroy(self.ctx, self.batch)
+            self._retire(self.batch)
         self.batch = nb.nbody_batch_create(self.ctx, off, [self.live[h]["prm"] for h in self.order],
                                            [self.live[h]["req"].dt for h in self.order],
                                            flags=nb.NB_BATCH_GRAPH if self.graph else 0)
         self.pack = pack
         self.dirty = False
 
+    def _retire(self, batch):
+        self.retired.append(batch)
+        if len(self.retired) >= 64:
+            self._free_retired()
+
+    def _free_retired(self):
+        for b in self.retired:
+            self.nb.nbody_batch_destroy(self.ctx, b)
+        self.retired.clear()
+
     def step(self, handles, nsteps):
         if self.dirty:
             self._repack()
-        self.nb.nbody_step_kdk_batched(self.ctx, self.batch, self.pack, nsteps)
+        self.nb.nbody_step_kdk_batched(self.ctx, self.batch, self.pack, nsteps, stream=self.stream)
         return {}
 
     def _release(self, handle):
@@ -284,17 +323,19 @@ class GpuBackend(Backend):
         del self.live[handle]
         self.dirty = True
         if not self.live and self.batch is not None:
-            self.nb.nbody_batch_destroy(self.ctx, self.batch)
+            self._retire(self.batch)
             self.batch, self.pack = None, None
 
     def finish(self, handle) -> Result:
         nb = self.nb
         e = self.live[handle]
         req, s, prm = e["req"], e["sys"], e["prm"]
-        d = nb.diag_dict(nb.nbody_diag(self.ctx, s, prm))
+        d = nb.diag_dict(nb.nbody_diag(self.ctx, s, prm, stream=self.stream)) if self.diagnostics else None
+        if self.keep_state:
+            self.stream.synchronize()
         state = s.numpy() if self.keep_state else None
         res = Result(req.id, req.n, req.steps, "fp64" if req.fp64 else "mixed", req.t_arrive, state=state, diag=d)
-        if not all(math.isfinite(v) for v in d.values()):
+        if d is not None and not all(math.isfinite(v) for v in d.values()):
             res.error = "non-finite state"
         self._release(handle)
         return res
@@ -303,6 +344,8 @@ class GpuBackend(Backend):
         self._release(handle)
 
     def close(self):
+        self.stream.synchronize()
         if self.batch is not None:
-            self.nb.nbody_batch_destroy(self.ctx, self.batch)
+            self._retire(self.batch)
             self.batch = None
+        self._free_retired()

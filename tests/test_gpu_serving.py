@@ -21,7 +21,7 @@ def stream():
 
 def test_mix_equals_alone_and_oracle(nb, ctx, orc):
     reqs = stream()
-    be = GpuBackend(ctx)
+    be = GpuBackend(ctx, graph=True)
     st = Scheduler(be, hbm_budget=8 << 30, max_tick_steps=4).run(reqs)
     be.close()
     assert all(r.error is None for r in st.results), [r.error for r in st.results]
