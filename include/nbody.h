@@ -31,8 +31,13 @@
  *             the halo field if enabled).
  *   Scratch.  Internal scratch grows on first use for a given size; after a
  *             warm-up call with the largest size, later calls allocate
- *             nothing (so they may be captured into a HIP graph).
+ *             nothing (so they may be captured into a HIP graph).  Outgrown
+ *             scratch stays allocated until the context is destroyed, so a
+ *             graph captured earlier stays valid.
  *   Threads.  A context is not thread-safe: use one per host thread or lock.
+ *             Calls on one context share its scratch, so calls on different
+ *             streams of one context must not run concurrently on the device
+ *             (order them, or use one context per stream).
  */
 #ifndef NBODY_H
 #define NBODY_H

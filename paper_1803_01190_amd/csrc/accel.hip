@@ -70,13 +70,21 @@ struct Lane {
     double km15, k0375;
     F tx[R], ty[R], tz[R], tp[R];            // inner sums
     O ox[R], oy[R], oz[R], op[R];            // outer sums (MIXED only)
+    // Equal-mass runs (float64): sums of the pair terms without the source
+    // mass, for sources of mass mrun not yet folded into tx.
+    double ux[R], uy[R], uz[R];
+    double mrun;
 };
 
-// One source against R targets.
-template <int PREC, int R, int MODE, bool SAFE>
+// One source against R targets.  UM (equal-mass run, accelerations only):
+// the source mass is left out of the pair term and applied once to the run's
+// sum (float64: fold(); mixed: the per-tile flush), saving one multiply per
+// pair.
+template <int PREC, int R, int MODE, bool SAFE, bool UM = false>
 __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy, double sz,
                                          double sm, float fx, float fy, float fz, float fm,
                                          int32_t lj, double eps2, float eps2f) {
+    static_assert(!UM || (MODE == MODE_ACC && PREC != P_FP32), "equal-mass runs: fp64/mixed accelerations");
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if constexpr (PREC == P_FP64) {
@@ -89,10 +97,17 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
             const double e = __builtin_fma(r2, y2, -1.0);
             if constexpr (MODE != MODE_PHI) {
                 const double c3 = __builtin_fma(L.km15, e, 1.0);
-                const double s = ((sm * y) * y2) * c3;
-                L.tx[r] = __builtin_fma(s, dx, L.tx[r]);
-                L.ty[r] = __builtin_fma(s, dy, L.ty[r]);
-                L.tz[r] = __builtin_fma(s, dz, L.tz[r]);
+                if constexpr (UM) {
+                    const double s = (y * y2) * c3;
+                    L.ux[r] = __builtin_fma(s, dx, L.ux[r]);
+                    L.uy[r] = __builtin_fma(s, dy, L.uy[r]);
+                    L.uz[r] = __builtin_fma(s, dz, L.uz[r]);
+                } else {
+                    const double s = ((sm * y) * y2) * c3;
+                    L.tx[r] = __builtin_fma(s, dx, L.tx[r]);
+                    L.ty[r] = __builtin_fma(s, dy, L.ty[r]);
+                    L.tz[r] = __builtin_fma(s, dz, L.tz[r]);
+                }
             }
             if constexpr (MODE != MODE_ACC) {
                 const double c1 = __builtin_fma(e, __builtin_fma(L.k0375, e, -0.5), 1.0);
@@ -109,7 +124,7 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
             float y = __builtin_amdgcn_rsqf(r2);
             if constexpr (SAFE) y = (r2 > 0.0f) ? y : 0.0f;
             if constexpr (MODE == MODE_PHI || MODE == MODE_ACC_PHI) y = (lj == L.li[r]) ? 0.0f : y;
-            const float my = fm * y;
+            const float my = UM ? y : fm * y;
             if constexpr (MODE != MODE_PHI) {
                 const float s = my * (y * y);
                 L.tx[r] = __builtin_fmaf(s, dx, L.tx[r]);
@@ -121,14 +136,40 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
     }
 }
 
+// End of a tile: the mixed path adds its float32 tile sums into float64,
+// scaled by the tile's mass when the tile was an equal-mass run (um).
 template <int PREC, int R>
-__device__ __forceinline__ void flush(Lane<PREC, R> &L) {
+__device__ __forceinline__ void flush(Lane<PREC, R> &L, bool um = false, double m0 = 1.0) {
     if constexpr (PREC == P_MIXED) {
+        if (um) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                L.ox[r] = __builtin_fma(m0, (double)L.tx[r], L.ox[r]);
+                L.oy[r] = __builtin_fma(m0, (double)L.ty[r], L.oy[r]);
+                L.oz[r] = __builtin_fma(m0, (double)L.tz[r], L.oz[r]);
+                L.tx[r] = L.ty[r] = L.tz[r] = 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                L.ox[r] += (double)L.tx[r]; L.oy[r] += (double)L.ty[r];
+                L.oz[r] += (double)L.tz[r]; L.op[r] += (double)L.tp[r];
+                L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0.0f;
+            }
+        }
+    }
+}
+
+// float64: add the pending equal-mass run, scaled by its mass, into tx.
+template <int PREC, int R>
+__device__ __forceinline__ void fold(Lane<PREC, R> &L) {
+    if constexpr (PREC == P_FP64) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            L.ox[r] += (double)L.tx[r]; L.oy[r] += (double)L.ty[r];
-            L.oz[r] += (double)L.tz[r]; L.op[r] += (double)L.tp[r];
-            L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0.0f;
+            L.tx[r] = __builtin_fma(L.mrun, L.ux[r], L.tx[r]);
+            L.ty[r] = __builtin_fma(L.mrun, L.uy[r], L.ty[r]);
+            L.tz[r] = __builtin_fma(L.mrun, L.uz[r], L.tz[r]);
+            L.ux[r] = L.uy[r] = L.uz[r] = 0.0;
         }
     }
 }
@@ -157,40 +198,79 @@ __device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int
         L.li[r] = (int32_t)(i - sys_off);
         L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0;
         L.ox[r] = L.oy[r] = L.oz[r] = L.op[r] = 0;
+        L.ux[r] = L.uy[r] = L.uz[r] = 0.0;
     }
+    L.mrun = 0.0;
 }
 
 // Sum sources [jb, je) (global indices; the system starts at sys_off) into L.
-// LDS-staged source tiles of BLOCK particles.
+// LDS-staged source tiles of BLOCK particles.  A tile whose sources all have
+// the same mass (decided by a block-wide vote, so the branch is uniform)
+// takes the equal-mass pair term.
 template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
 __device__ __forceinline__ void sweep_lds(Lane<PREC, R> &L, const State &st, int64_t jb,
                                           int64_t je, int64_t sys_off, double eps2, float eps2f,
                                           typename Tr<PREC>::J *tile) {
+    constexpr bool kUM = MODE == MODE_ACC && PREC != P_FP32;
     const int t = threadIdx.x;
     for (int64_t jt = jb; jt < je; jt += BLOCK) {
         const int64_t j = jt + t;
-        tile[t] = load_src<PREC>(st, j, j < je);
+        const typename Tr<PREC>::J mine = load_src<PREC>(st, j, j < je);
+        tile[t] = mine;
         __syncthreads();
         const int32_t lj0 = (int32_t)(jt - sys_off);
-#pragma unroll 4
-        for (int k = 0; k < BLOCK; ++k) {
-            const typename Tr<PREC>::J e = tile[k];
-            if constexpr (PREC == P_FP32)
-                interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, e.x, e.y, e.z, e.m, lj0 + k, eps2, eps2f);
-            else if constexpr (PREC == P_MIXED)
-                interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, 0, 0, 0, 0, e.m, lj0 + k, eps2, eps2f);
-            else
-                interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, e.m, 0, 0, 0, 0, lj0 + k, eps2, eps2f);
+        bool um = false;
+        double m0 = 0.0;
+        if constexpr (kUM) {
+            m0 = (double)tile[0].m;
+            um = __syncthreads_and((double)mine.m == m0) != 0;
         }
-        flush(L);
+        if (um) {
+            if constexpr (kUM) {
+                if constexpr (PREC == P_FP64) {
+                    if (m0 != L.mrun) { fold(L); L.mrun = m0; }
+                }
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k) {
+                    const typename Tr<PREC>::J e = tile[k];
+                    interact<PREC, R, MODE, SAFE, true>(L, e.x, e.y, e.z, 0, 0, 0, 0, 0, lj0 + k, eps2, eps2f);
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < BLOCK; ++k) {
+                const typename Tr<PREC>::J e = tile[k];
+                if constexpr (PREC == P_FP32)
+                    interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, e.x, e.y, e.z, e.m, lj0 + k, eps2, eps2f);
+                else if constexpr (PREC == P_MIXED)
+                    interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, 0, 0, 0, 0, e.m, lj0 + k, eps2, eps2f);
+                else
+                    interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, e.m, 0, 0, 0, 0, lj0 + k, eps2, eps2f);
+            }
+        }
+        flush(L, um, m0);
         __syncthreads();
     }
+    fold(L);
+}
+
+// True if every source in [jb, je) has the same mass (bitwise), decided by
+// the whole workgroup (strided vector loads and a block vote).
+template <int BLOCK>
+__device__ __forceinline__ bool range_equal_mass(const double *m, int64_t jb, int64_t je) {
+    if (jb >= je) return false;
+    const uint64_t b0 = __builtin_bit_cast(uint64_t, m[jb]);
+    int ok = 1;
+    for (int64_t j = jb + threadIdx.x; j < je; j += BLOCK) ok &= __builtin_bit_cast(uint64_t, m[j]) == b0;
+    return __syncthreads_and(ok) != 0;
 }
 
 // Same sum with sources read as wave-uniform values (scalar loads into
 // SGPRs).  Groups of U sources; the tail is summed one source at a time so
-// nothing past je is read.
-template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
+// nothing past je is read.  UM: every source of the range has mass L.mrun
+// (checked by the caller), so masses are not read and the run is folded in
+// once at the end.
+template <int PREC, int R, int BLOCK, int MODE, bool SAFE, bool UM>
 __device__ __forceinline__ void sweep_scalar(Lane<PREC, R> &L, const State &st, int64_t jb,
                                              int64_t je, int64_t sys_off, double eps2,
                                              float eps2f) {
@@ -205,30 +285,52 @@ __device__ __forceinline__ void sweep_scalar(Lane<PREC, R> &L, const State &st, 
     for (; j + U <= je; j += U) {
         double sx[U], sy[U], sz[U], sm[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) { sx[u] = X[j + u]; sy[u] = Y[j + u]; sz[u] = Z[j + u]; sm[u] = M[j + u]; }
+        for (int u = 0; u < U; ++u) {
+            sx[u] = X[j + u]; sy[u] = Y[j + u]; sz[u] = Z[j + u];
+            sm[u] = UM ? 0.0 : M[j + u];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t lj = (int32_t)(j + u - sys_off);
-            if constexpr (PREC == P_FP32)
+            if constexpr (UM)
+                interact<PREC, R, MODE, SAFE, true>(L, sx[u], sy[u], sz[u], 0, 0, 0, 0, 0, lj, eps2, eps2f);
+            else if constexpr (PREC == P_FP32)
                 interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, (float)sx[u], (float)sy[u], (float)sz[u], (float)sm[u], lj, eps2, eps2f);
             else if constexpr (PREC == P_MIXED)
                 interact<PREC, R, MODE, SAFE>(L, sx[u], sy[u], sz[u], 0, 0, 0, 0, (float)sm[u], lj, eps2, eps2f);
             else
                 interact<PREC, R, MODE, SAFE>(L, sx[u], sy[u], sz[u], sm[u], 0, 0, 0, 0, lj, eps2, eps2f);
         }
-        if (j + U >= flush_at) { flush(L); flush_at += BLOCK; }
+        if (j + U >= flush_at) { flush(L, UM, L.mrun); flush_at += BLOCK; }
     }
     for (; j < je; ++j) {
-        const double sx = X[j], sy = Y[j], sz = Z[j], sm = M[j];
+        const double sx = X[j], sy = Y[j], sz = Z[j], sm = UM ? 0.0 : M[j];
         const int32_t lj = (int32_t)(j - sys_off);
-        if constexpr (PREC == P_FP32)
+        if constexpr (UM)
+            interact<PREC, R, MODE, SAFE, true>(L, sx, sy, sz, 0, 0, 0, 0, 0, lj, eps2, eps2f);
+        else if constexpr (PREC == P_FP32)
             interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, (float)sx, (float)sy, (float)sz, (float)sm, lj, eps2, eps2f);
         else if constexpr (PREC == P_MIXED)
             interact<PREC, R, MODE, SAFE>(L, sx, sy, sz, 0, 0, 0, 0, (float)sm, lj, eps2, eps2f);
         else
             interact<PREC, R, MODE, SAFE>(L, sx, sy, sz, sm, 0, 0, 0, 0, lj, eps2, eps2f);
     }
-    flush(L);
+    flush(L, UM, L.mrun);
+    fold(L);
+}
+
+template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
+__device__ __forceinline__ void sweep_scalar_any(Lane<PREC, R> &L, const State &st, int64_t jb,
+                                                 int64_t je, int64_t sys_off, double eps2,
+                                                 float eps2f) {
+    if constexpr (MODE == MODE_ACC && PREC != P_FP32) {
+        if (range_equal_mass<BLOCK>(st.m, jb, je)) {
+            L.mrun = st.m[jb];
+            sweep_scalar<PREC, R, BLOCK, MODE, SAFE, true>(L, st, jb, je, sys_off, eps2, eps2f);
+            return;
+        }
+    }
+    sweep_scalar<PREC, R, BLOCK, MODE, SAFE, false>(L, st, jb, je, sys_off, eps2, eps2f);
 }
 
 // Raw sums of lane slot r (outer for MIXED, inner otherwise).
@@ -287,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(PairLaunch P, int64_t chunk) {
     if constexpr (JSRC == 0)
         sweep_lds<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f, tile);
     else
-        sweep_scalar<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f);
+        sweep_scalar_any<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f);
     const int64_t rows = P.i1 - P.i0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {

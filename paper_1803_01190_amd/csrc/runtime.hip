@@ -35,6 +35,10 @@ struct nbody_ctx {
     double *phi = nullptr;
     size_t phi_cap = 0;    // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
+    // Scratch outgrown by a larger call is kept (not freed) until the
+    // context is destroyed: a HIP graph captured earlier may still use it,
+    // and freeing would synchronise the device.
+    std::vector<void *> retired;
     hipStream_t cap = nullptr; // capture stream for batched graphs
     std::map<std::pair<int, int>, nbody_plan> plans;
     // kernel timing
@@ -185,18 +189,19 @@ nbody_plan plan_for(nbody_ctx *ctx, int prec, int64_t n) {
 
 nbody_status ensure(nbody_ctx *ctx, double **buf, size_t *cap, size_t need) {
     if (need <= *cap) return NB_OK;
-    if (*buf) {
-        HIPCHECK(ctx, hipDeviceSynchronize());
-        HIPCHECK(ctx, hipFree(*buf));
-        *buf = nullptr;
-        *cap = 0;
-    }
-    hipError_t e = hipMalloc((void **)buf, need * sizeof(double));
+    // grow geometrically so a sequence of growing calls retires little memory
+    size_t want = std::max(need, *cap + *cap / 2);
+    double *nbuf = nullptr;
+    hipError_t e = hipMalloc((void **)&nbuf, want * sizeof(double));
     if (e != hipSuccess) {
-        *buf = nullptr;
-        return fail(ctx, NB_ENOMEM, "hipMalloc of %zu bytes failed: %s", need * sizeof(double), hipGetErrorString(e));
+        want = need;
+        e = hipMalloc((void **)&nbuf, want * sizeof(double));
     }
-    *cap = need;
+    if (e != hipSuccess)
+        return fail(ctx, NB_ENOMEM, "hipMalloc of %zu bytes failed: %s", want * sizeof(double), hipGetErrorString(e));
+    if (*buf) ctx->retired.push_back(*buf);
+    *buf = nbuf;
+    *cap = want;
     return NB_OK;
 }
 
@@ -291,6 +296,7 @@ nbody_plan mode_plan(nbody_ctx *ctx, int prec, int64_t n, int mode) {
     if (mode == MODE_ACC) return plan_for(ctx, prec, n);
     // the potential variants exist for one shape only: R = 1, 256 lanes, LDS
     nbody_plan pl{1, 256, 1, 0};
+    if (prec == P_FP32) return pl;  // one float32 running sum, as in plan_for
     const int64_t nblk = (n + 255) / 256;
     while (nblk * pl.split < 2LL * ctx->cus && n / (2LL * pl.split) >= 512 && pl.split < 64) pl.split *= 2;
     return pl;
@@ -408,6 +414,7 @@ nbody_status nbody_ctx_destroy(nbody_ctx *ctx) {
     for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->phi) (void)hipFree(ctx->phi);
+    for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->sysc) (void)hipFree(ctx->sysc);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;

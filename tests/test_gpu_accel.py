@@ -183,3 +183,32 @@ def test_empty_and_validation(nb, ctx):
         nb.nbody_accel_rows(ctx, s, prm, 5, 11)
     with pytest.raises(nb.NBodyError):
         nb.nbody_plan_set(ctx, nb.NB_FP64, 10, {"R": 3, "block": 256, "split": 1})
+
+
+def _mass_patterns(n, seed):
+    st = wl.Stream(seed)
+    base = np.full(n, 1.0 / n)
+    rand = 0.5 / n + st.uniform(n) / n                      # every mass different
+    halves = base.copy()
+    halves[n // 2:] *= 3.0                                  # two uniform runs
+    odd = base.copy()
+    odd[n // 3] *= 2.0                                      # uniform but for one source
+    blocks = base * (1 + (np.arange(n) // 300) % 3)          # runs that cross tile edges
+    return {"random": rand, "halves": halves, "odd": odd, "runs": blocks}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("jsrc", [0, 1])
+@pytest.mark.parametrize("pattern", ["random", "halves", "odd", "runs"])
+def test_mass_patterns(nb, ctx, orc, prec, jsrc, pattern):
+    # equal-mass source runs take a shorter pair term; every mix of runs and
+    # unequal masses must still match the oracle
+    n = 2 * 1024 + 77
+    ic = wl.plummer(n, 41)
+    ic["m"] = _mass_patterns(n, 42)[pattern]
+    ref, _, A = oracle_accel(orc, ic, 0.01)
+    got = run_accel(nb, ctx, ic, 0.01, nb.PREC[prec], plan=dict(R=2, block=256, split=3, jsrc=jsrc))
+    e = errs(got, ref, A)
+    tol = {"eps_rms": FP64_TOL, "eps_cond": FP64_TOL} if prec == "fp64" else MIXED_TOL
+    for k, v in tol.items():
+        assert e[k] <= v, (prec, jsrc, pattern, e)

@@ -1,0 +1,97 @@
+"""Runtime properties on the GPU: checkpoint/resume continues bitwise, the
+single-system step can be captured into a HIP graph and replayed (with eager
+work and synchronisations between replays), kernel timing is recorded, and
+the autotuner returns a valid plan."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+K = ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_checkpoint_resume_bitwise(nb, ctx, tmp_path, prec):
+    from paper_1803_01190_amd import checkpoint
+    ic = wl.exp_disk(3000, 31)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.PREC[prec], halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    a = nb.System.from_arrays(ic)
+    nb.nbody_accel(ctx, a, prm)
+    nb.nbody_step_kdk(ctx, a, prm, 1e-3, 10)
+    b = nb.System.from_arrays(ic)
+    nb.nbody_accel(ctx, b, prm)
+    nb.nbody_step_kdk(ctx, b, prm, 1e-3, 4)
+    path = str(tmp_path / "snap.npz")
+    checkpoint.save(path, b, prm, t=4e-3, step=4)
+    del b
+    c, prm2, t, step, _ = checkpoint.load(path)
+    assert step == 4 and prm2 == prm
+    nb.nbody_step_kdk(ctx, c, prm2, 1e-3, 6)
+    torch.cuda.synchronize()
+    for k in K:
+        assert torch.equal(a[k], c[k]), k
+
+
+@pytest.mark.parametrize("scheme", ["kdk", "o4"])
+def test_single_system_graph_capture(nb, ctx, scheme):
+    ic = wl.plummer(5000, 32)
+    prm = nb.Params(eps=0.01, prec=nb.NB_MIXED)
+    step = nb.nbody_step_kdk if scheme == "kdk" else nb.nbody_step_o4
+    eager = nb.System.from_arrays(ic)
+    cap = nb.System.from_arrays(ic)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for sys in (eager, cap):
+            nb.nbody_accel(ctx, sys, prm, stream=s)
+        step(ctx, cap, prm, 1e-3, 1, stream=s)    # warm-up: scratch is allocated here
+        step(ctx, eager, prm, 1e-3, 1, stream=s)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        step(ctx, cap, prm, 1e-3, 2, stream=s)
+    for rep in range(4):
+        g.replay()
+        step(ctx, eager, prm, 1e-3, 2)
+        junk = torch.randn(4096, device="cuda").cumsum(0)  # unrelated eager work
+        torch.cuda.synchronize()
+        for k in K:
+            assert torch.equal(eager[k], cap[k]), (scheme, rep, k)
+    del junk
+
+
+def test_profile_counts_launches(nb, ctx):
+    ic = wl.plummer(4096, 33)
+    prm = nb.Params(eps=0.01, prec=nb.NB_FP64)
+    s = nb.System.from_arrays(ic)
+    nb.nbody_accel(ctx, s, prm)
+    nb.nbody_profile_read(ctx)
+    nb.nbody_profile_enable(ctx, True)
+    nb.nbody_step_kdk(ctx, s, prm, 1e-3, 3)
+    nb.nbody_profile_enable(ctx, False)
+    p = nb.nbody_profile_read(ctx)
+    assert p["accel_launches"] == 3 and p["update_launches"] == 3
+    assert p["interactions"] == 3 * 4096 * 4096 and p["accel_ms"] > 0
+    assert nb.nbody_profile_read(ctx)["accel_launches"] == 0  # read resets
+
+
+def test_autotune_returns_a_valid_plan(nb, ctx, orc):
+    n = 3000
+    plan = nb.nbody_autotune(ctx, nb.NB_FP64, n, 200.0)
+    assert plan["R"] in (1, 2, 4) and plan["block"] in (128, 256) and plan["split"] >= 1
+    assert nb.nbody_plan_get(ctx, nb.NB_FP64, n) == plan
+    ic = wl.plummer(n, 34)
+    s = nb.System.from_arrays(ic)
+    nb.nbody_accel(ctx, s, nb.Params(eps=0.01))
+    ax, ay, az, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], 1.0, 0.01, want_scale=True)
+    got = s.numpy()
+    d = np.sqrt((got["ax"] - ax) ** 2 + (got["ay"] - ay) ** 2 + (got["az"] - az) ** 2)
+    assert np.max(d / A) <= 1e-12
+    nb.nbody_plan_set(ctx, nb.NB_FP64, n, None)
+    # the float32 path never splits its running sum, whatever the plan says
+    nb.nbody_plan_set(ctx, nb.NB_FP32, n, {"R": 2, "block": 128, "split": 8, "jsrc": 0})
+    assert nb.nbody_plan_get(ctx, nb.NB_FP32, n)["split"] == 1
+    nb.nbody_plan_set(ctx, nb.NB_FP32, n, None)
