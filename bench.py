@@ -84,10 +84,17 @@ def main():
                          "tuned_plans.json when it has this size, else autotune")
     ap.add_argument("--retune", action="store_true", help="autotune even if a cached plan exists")
     ap.add_argument("--plans-out", default=None, help="write the plans used in plan-cache form")
-    ap.add_argument("--workload", default="disk", choices=["disk", "batched", "serving", "integrators"],
+    ap.add_argument("--workload", default="disk",
+                    choices=["disk", "batched", "serving", "integrators", "longrun"],
                     help="disk: the headline N=2^20 step (default); batched: 256 independent systems "
                          "in one persistent launch vs one launch per system; serving: Poisson "
-                         "request stream through the continuous-batching loop")
+                         "request stream through the continuous-batching loop; longrun: 10^4-step "
+                         "self-gravitating disk in each precision (conservation and density maps)")
+    ap.add_argument("--long-n", type=int, default=1 << 17, help="longrun: particles")
+    ap.add_argument("--long-steps", type=int, default=10000, help="longrun: steps per run")
+    ap.add_argument("--long-runs", default="fp64,fp64_alt,mixed,fp32",
+                    help="longrun: runs (fp64_alt: float64 with another summation order)")
+    ap.add_argument("--out-dir", default="gpurun_out/longrun", help="longrun: series and maps")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
     ap.add_argument("--graph", action="store_true", help="serving: replay steps from HIP graphs")
     ap.add_argument("--profile-run", action="store_true",
@@ -96,8 +103,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU target split is a design in DESIGN.md, not a run)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(splitting the targets across GPUs is designed but not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -113,6 +120,8 @@ def main():
         return bench_serving(args)
     if args.workload == "integrators":
         return bench_integrators(args)
+    if args.workload == "longrun":
+        return bench_longrun(args)
     dev = torch.device("cuda:0")
     n, dt, eps = args.n, 1e-3, 0.02
     halo = wl.default_halo()
@@ -413,6 +422,79 @@ def bench_integrators(args):
            "config": {"workload": "exponential disk N=2^17 + halo, eps=0.02, T=1; reference fp64 O4 dt=5e-4 "
                                   "on the GPU", "n": n},
            "force_error_rms_vs_fp64": ferr, "runs": runs}
+    print(json.dumps(res))
+    ctx.close()
+
+
+def bench_longrun(args):
+    """The paper's precision study (Section 3, Table 2, Figs. 5-7) on the
+    completely self-gravitating exponential disk (no halo, eps = 0.02):
+    --long-steps leapfrog steps with the paper's ratio of about 4000 steps per
+    rotation at the disk's edge, once per precision and once more in float64
+    with another summation order (a control: the system is chaotic, so any
+    rounding difference grows; what precision adds shows against that).
+    Records the largest deviations of P, Lz, E and the centre of mass, their
+    time series, and surface-density maps compared with the float64 run."""
+    import numpy as np
+
+    import workloads as wl
+    from paper_1803_01190_amd import longrun as lr
+    from paper_1803_01190_amd import nbody as nb
+
+    n, steps, seed, eps = args.long_n, args.long_steps, 3, 0.02
+    halo = wl.no_halo()
+    period = wl.outer_period(halo=halo)
+    dt = period / 4000.0
+    ic = wl.make("disk_sg", n, seed)
+    ctx = nb.Context(0)
+    nb.load_plans(ctx.h)
+    grid = lr.Grid(256, 256, -6.0, -6.0, 12.0 / 256)
+    maps_at = [steps * k // 10 for k in range(11)]
+    alt_plan = {"R": 2, "block": 256, "split": 1, "jsrc": 0}
+    os.makedirs(args.out_dir, exist_ok=True)
+    recs, out = {}, {}
+    for name in args.long_runs.split(","):
+        prec = "fp64" if name == "fp64_alt" else name
+        prm = nb.Params(eps=eps, prec=nb.PREC[prec])
+        plan = alt_plan if name == "fp64_alt" else None
+        t0 = time.perf_counter()
+
+        def progress(done, rec, name=name, t0=t0):
+            if done % 1000 == 0 or done == steps:
+                dv = rec.deviations()
+                log(f"[longrun] {name} step {done}/{steps} ({time.perf_counter() - t0:.0f}s) "
+                    f"dE {dv['dE_rel'][-1]:.2e} dL {dv['dL_rel'][-1]:.2e} dP {dv['dP_abs'][-1]:.2e}")
+
+        rec = lr.run(ctx.h, ic, prm, dt, steps, every=50, maps_at=maps_at, grid=grid, plan=plan,
+                     progress=progress)
+        recs[name] = rec
+        out[name] = {**rec.table2(), "wall_s": rec.busy_s, "evals": rec.evals,
+                     "pair_interactions_per_s": lr.interactions_per_s(n, rec)}
+        log(f"[longrun] {name}: {out[name]}")
+    ref = recs.get("fp64")
+    maps = {}
+    if ref is not None:
+        for name, rec in recs.items():
+            if name == "fp64":
+                continue
+            maps[name] = {str(k): lr.compare_maps(ref.maps[k], rec.maps[k]) for k in maps_at}
+        maps["fp64_m2"] = {str(k): lr.nonaxisymmetry(ref.maps[k], grid) for k in maps_at}
+    series = {name: {"step": rec.steps, **{k: v.tolist() for k, v in rec.deviations().items()}}
+              for name, rec in recs.items()}
+    with open(os.path.join(args.out_dir, f"longrun_{n}.json"), "w") as f:
+        json.dump({"n": n, "dt": dt, "steps": steps, "eps": eps, "period": period, "table2": out,
+                   "maps": maps, "series": series}, f)
+    np.savez_compressed(os.path.join(args.out_dir, f"maps_{n}.npz"),
+                        **{f"{name}_{k}": rec.maps[k] for name, rec in recs.items() for k in maps_at})
+    head = "mixed" if "mixed" in out else next(iter(out))
+    res = {"metric": "10^4-step conservation (Table 2 quantities) and density-map deviation vs float64",
+           "value": out[head]["pair_interactions_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,
+           "steps": steps, "warmup": 0, "ms_per_step": 1e3 * out[head]["wall_s"] / steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[
+               "fp64" if head == "fp64_alt" else head], "data": "synthetic",
+           "config": {"workload": f"self-gravitating exponential disk N={n} (no halo), eps={eps}, "
+                                  f"KDK dt={dt:.6g} (outer period / 4000), seed {seed}", "n": n},
+           "table2": out, "maps": maps}
     print(json.dumps(res))
     ctx.close()
 

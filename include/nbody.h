@@ -196,6 +196,23 @@ NBODY_API nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody
 NBODY_API nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                         nbody_diag_t *out_dev, void *stream);
 
+/* Surface-density map of a system projected on the x-y plane (the maps by
+ * which Section 3, Fig. 7 compares single- and double-precision disks):
+ *   counts[iy * nx + ix] = number of particles with
+ *   ix = floor((x - x0) * sx), iy = floor((y - y0) * sy),
+ *   0 <= ix < nx, 0 <= iy < ny.
+ * Each index is decided in float64 by one subtraction and one
+ * multiplication (not fused); particles off the grid or with a NaN
+ * coordinate are not counted.  The surface density of cell (ix, iy) is
+ * m * counts / (1 / (sx sy)) for particles of equal mass m.
+ * Reads sys->n, x and y only.  counts: DEVICE array of nx * ny uint32,
+ * overwritten in stream order.  Integer counts: the result is exact and
+ * independent of launch order.  NB_EINVAL: NULL pointers, nx or ny < 1,
+ * nx * ny > 2^26, sx or sy not finite and > 0, x0 or y0 not finite. */
+NBODY_API nbody_status nbody_surface_density(nbody_ctx *ctx, const nbody_sys *sys, int32_t nx, int32_t ny,
+                                             double x0, double y0, double sx, double sy,
+                                             uint32_t *counts, void *stream);
+
 /* ---- many independent systems in one launch ---------------------------- */
 
 /* flags for nbody_batch_create */

@@ -54,7 +54,7 @@ class Halo:
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int64)
-_i64, _dbl, _int = ctypes.c_int64, ctypes.c_double, ctypes.c_int
+_i64, _dbl, _int, _int32 = ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int32
 
 
 def load_library(path: str | None = None):
@@ -81,6 +81,14 @@ def _load(path: str | None = None):
         lib.orc_step_o4.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp,
                                     _dbl, _i64, _dbl, _dbl, _int, _int]
         lib.orc_diag.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _D, _int]
+        lib.orc_accel_jerk.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _D, _D, _D, _D,
+                                       _D, _D, _int]
+        lib.orc_step_hermite.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl,
+                                         _dbl, hp, _dbl, _i64, _int]
+        lib.orc_step_rk4.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _dbl,
+                                     _i64, _int]
+        lib.orc_surface_density.argtypes = [_i64, _D, _D, _int32, _int32, _dbl, _dbl, _dbl, _dbl,
+                                            ctypes.POINTER(ctypes.c_uint32)]
         lib.orc_force_evals.restype = _i64
         lib.orc_max_threads.restype = _int
         _lib = lib
@@ -179,6 +187,28 @@ class State:
                              int(paper_form), int(self.reverse_j), self.nthreads)
         return self
 
+    def init_jerk(self):
+        """Acceleration and jerk at the current state (for step_hermite)."""
+        a = self.a
+        out = accel_jerk(a, self.G, self.eps, self.halo, self.nthreads)
+        for k, v in zip(("ax", "ay", "az", "jx", "jy", "jz"), out):
+            a[k] = v
+        return self
+
+    def step_hermite(self, dt, nsteps=1):
+        if "jx" not in self.a:
+            self.init_jerk()
+        hp, _keep = _halo(self.halo)
+        a = self.a
+        _load().orc_step_hermite(self.n, *self._ptrs(), _p(a["jx"]), _p(a["jy"]), _p(a["jz"]), self.G,
+                                 self.eps, hp, dt, nsteps, self.nthreads)
+        return self
+
+    def step_rk4(self, dt, nsteps=1):
+        hp, _keep = _halo(self.halo)
+        _load().orc_step_rk4(self.n, *self._ptrs(), self.G, self.eps, hp, dt, nsteps, self.nthreads)
+        return self
+
     def step_o4(self, dt, nsteps=1, w1=YOSHIDA_W1, w0=YOSHIDA_W0):
         hp, _keep = _halo(self.halo)
         _load().orc_step_o4(self.n, *self._ptrs(), self.G, self.eps, hp, dt, nsteps, w1, w0,
@@ -208,6 +238,30 @@ def diag(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0) -> dict:
     lib.orc_diag(a["x"].size, _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["vx"]), _p(a["vy"]),
                  _p(a["vz"]), _p(a["m"]), G, eps, hp, _p(out), nthreads)
     return dict(zip(DIAG_KEYS, out.tolist()))
+
+
+def accel_jerk(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0):
+    """Acceleration (Eqs. (1)-(2)) and its time derivative along the motion,
+    plus the halo's when given.  Returns (ax, ay, az, jx, jy, jz)."""
+    lib = _load()
+    a = {k: _f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
+    n = a["x"].size
+    out = [np.zeros(n) for _ in range(6)]
+    hp, _keep = _halo(halo)
+    lib.orc_accel_jerk(n, *[_p(a[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], G, eps, hp,
+                       *[_p(o) for o in out], nthreads)
+    return tuple(out)
+
+
+def surface_density(x, y, nx, ny, x0, y0, sx, sy) -> np.ndarray:
+    """Particle counts per x-y cell, shape (ny, nx), uint32: the surface-density
+    maps of Section 3 (Fig. 7).  Cell index floor((x - x0) * sx) in float64."""
+    x, y = _f64(x), _f64(y)
+    assert x.shape == y.shape
+    out = np.zeros((ny, nx), dtype=np.uint32)
+    _load().orc_surface_density(x.size, _p(x), _p(y), int(nx), int(ny), float(x0), float(y0), float(sx),
+                                float(sy), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return out
 
 
 def force_evals() -> int:

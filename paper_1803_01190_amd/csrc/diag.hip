@@ -6,6 +6,8 @@
 // combined by a fixed xor-butterfly inside each wave (DPP / ds_swizzle
 // shuffles) and the four wave sums in wave order, so the result is
 // bitwise reproducible for a given n.  Always float64.
+#include <algorithm>
+
 #include "nbody_internal.h"
 #include "halo.h"
 
@@ -66,7 +68,40 @@ __global__ __launch_bounds__(kThreads) void k_diag(State st, const double *phi, 
     }
 }
 
+// Surface-density map: one integer atomic per particle on the grid.  The
+// float64 index (x - x0) * sx is compared before the conversion, so NaN and
+// off-grid particles drop out and the conversion of t >= 0 is floor(t).
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t *p, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) p[k] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_surface_density(const double *x, const double *y, int64_t n,
+                                                         int32_t nx, int32_t ny, double x0, double y0,
+                                                         double sx, double sy, uint32_t *counts) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double tx = __dmul_rn(x[i] - x0, sx);
+        const double ty = __dmul_rn(y[i] - y0, sy);
+        if (tx >= 0.0 && tx < (double)nx && ty >= 0.0 && ty < (double)ny) {
+            const int64_t c = (int64_t)(int32_t)ty * nx + (int32_t)tx;
+            atomicAdd(counts + c, 1u);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_surface_density(const double *x, const double *y, int64_t n, int32_t nx, int32_t ny,
+                                  double x0, double y0, double sx, double sy, uint32_t *counts,
+                                  hipStream_t s) {
+    const int64_t cells = (int64_t)nx * ny;
+    const unsigned gz = (unsigned)std::min<int64_t>((cells + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_u32, dim3(gz), dim3(256), 0, s, counts, cells);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_surface_density, dim3(g), dim3(256), 0, s, x, y, n, nx, ny, x0, y0, sx, sy, counts);
+    return hipGetLastError();
+}
 
 hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst *sys, int32_t B,
                               double *out, hipStream_t s) {

@@ -92,6 +92,9 @@ hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst
                               int32_t B, double *out, hipStream_t s);
 
 // Small utilities.
+hipError_t launch_surface_density(const double *x, const double *y, int64_t n, int32_t nx, int32_t ny,
+                                  double x0, double y0, double sx, double sy, uint32_t *counts,
+                                  hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // write one SysConst into device memory (graph-capturable, no host staging)
 hipError_t launch_set_sysconst(SysConst *dst, const SysConst &v, hipStream_t s);

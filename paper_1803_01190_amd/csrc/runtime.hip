@@ -533,6 +533,30 @@ nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params
     }
 }
 
+nbody_status nbody_surface_density(nbody_ctx *ctx, const nbody_sys *sys, int32_t nx, int32_t ny, double x0,
+                                   double y0, double sx, double sy, uint32_t *counts, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        if (!sys) return fail(ctx, NB_EINVAL, "sys is NULL");
+        if (sys->n < 0 || sys->n > INT32_MAX)
+            return fail(ctx, NB_EINVAL, "n must be in [0, 2^31) (got %lld)", (long long)sys->n);
+        if (sys->n > 0 && (!sys->x || !sys->y)) return fail(ctx, NB_EINVAL, "x or y is NULL");
+        if (!counts) return fail(ctx, NB_EINVAL, "counts is NULL");
+        if (nx < 1 || ny < 1 || (int64_t)nx * ny > (int64_t)1 << 26)
+            return fail(ctx, NB_EINVAL, "grid %d x %d: need nx, ny >= 1 and nx * ny <= 2^26", nx, ny);
+        if (!(is_finite(sx) && sx > 0.0 && is_finite(sy) && sy > 0.0))
+            return fail(ctx, NB_EINVAL, "sx and sy must be finite and > 0");
+        if (!(is_finite(x0) && is_finite(y0))) return fail(ctx, NB_EINVAL, "x0 and y0 must be finite");
+        DevGuard g(ctx->device);
+        const hipError_t e = launch_surface_density(sys->x, sys->y, sys->n, nx, ny, x0, y0, sx, sy, counts,
+                                                    (hipStream_t)stream);
+        if (e != hipSuccess) return hipfail(ctx, e, "surface density launch");
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_surface_density");
+    }
+}
+
 // ---- batched ---------------------------------------------------------------
 
 nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off, const nbody_params *prm,

@@ -74,6 +74,7 @@ def _load():
         "nbody_step_kdk": ([P, S, PR, D, I64, V]),
         "nbody_step_o4": ([P, S, PR, D, I64, V]),
         "nbody_diag": ([P, S, PR, V, V]),
+        "nbody_surface_density": ([P, S, I32, I32, D, D, D, D, V, V]),
         "nbody_batch_create": ([P, I32, ctypes.POINTER(I64), PR, ctypes.POINTER(D), ctypes.c_uint32,
                                 ctypes.POINTER(P)]),
         "nbody_batch_destroy": ([P, P]),
@@ -209,6 +210,20 @@ def nbody_diag(ctx, sys: System, prm: Params, out: torch.Tensor | None = None, s
     cs, cp = sys.c(), prm.c()
     _check(ctx, _lib.nbody_diag(ctx, ctypes.byref(cs), ctypes.byref(cp), ctypes.c_void_p(out.data_ptr()),
                                 _stream(stream)))
+    return out
+
+
+def nbody_surface_density(ctx, sys: System, nx: int, ny: int, x0: float, y0: float, sx: float, sy: float,
+                          out: torch.Tensor | None = None, stream=None):
+    """Counts of particles per x-y cell, an int32 device tensor of shape
+    (ny, nx) holding the library's uint32 counts (n < 2^31)."""
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.int32, device=sys.t["x"].device)
+    assert out.dtype == torch.int32 and out.is_contiguous() and out.numel() == nx * ny
+    cs = sys.c()
+    _check(ctx, _lib.nbody_surface_density(ctx, ctypes.byref(cs), int(nx), int(ny), float(x0), float(y0),
+                                           float(sx), float(sy), ctypes.c_void_p(out.data_ptr()),
+                                           _stream(stream)))
     return out
 
 

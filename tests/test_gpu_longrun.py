@@ -1,0 +1,51 @@
+"""The long-run driver on the GPU against the oracle: a float64 run of the
+self-gravitating disk samples E, P, Lz and the centre of mass along the way
+and maps the surface density; each sample must match the oracle's run of the
+same steps, and the largest deviations (the Table 2 columns) must agree."""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fp64_series_match_oracle(nb, ctx, orc):
+    from paper_1803_01190_amd import longrun as lr
+    n, steps, every, eps = 2048, 120, 40, 0.02
+    halo = wl.no_halo()
+    dt = wl.outer_period(halo=halo) / 4000.0
+    ic = wl.make("disk_sg", n, 7)
+    grid = lr.Grid(64, 64, -6.0, -6.0, 12.0 / 64)
+    print(f"[case] longrun fp64 n={n} steps={steps}", flush=True)
+    rec = lr.run(ctx, ic, nb.Params(eps=eps, prec=nb.NB_FP64), dt, steps, every=every,
+                 maps_at=(0, 60, steps), grid=grid)
+    assert rec.steps == [0, 40, 80, 120] and rec.evals == steps
+    ref = orc.State(ic, eps=eps)
+    want = {"E": [], "P": [], "Lz": [], "com": []}
+    for k in range(len(rec.steps)):
+        if k:
+            ref.step_kdk(dt, every)
+        d = ref.diag()
+        want["E"].append(d["E"])
+        want["P"].append((d["Px"], d["Py"], d["Pz"]))
+        want["Lz"].append(d["Lz"])
+        want["com"].append((d["Cx"], d["Cy"], d["Cz"]))
+    E, Ew = np.asarray(rec.E), np.asarray(want["E"])
+    assert np.max(np.abs(E - Ew) / abs(Ew[0])) <= 1e-11
+    assert np.max(np.abs(np.asarray(rec.Lz) - want["Lz"]) / abs(want["Lz"][0])) <= 1e-11
+    # total momentum and centre of mass stay at round-off in both
+    assert np.max(np.abs(np.asarray(rec.P))) <= 1e-13 and np.max(np.abs(want["P"])) <= 1e-13
+    assert np.max(np.abs(np.asarray(rec.com) - np.asarray(want["com"]))) <= 1e-11
+    t2 = rec.table2()
+    assert t2["dP_abs_max"] <= 1e-13 and t2["dL_rel_max"] <= 1e-12
+    assert t2["dE_rel_max"] > 0.0
+    # maps: identical input gives identical counts; after 120 steps the
+    # trajectories differ only by round-off, far below a cell
+    assert np.array_equal(rec.maps[0], orc.surface_density(ic["x"], ic["y"], *grid.args()))
+    fin = orc.surface_density(ref["x"], ref["y"], *grid.args())
+    assert int(np.abs(rec.maps[steps].astype(np.int64) - fin).sum()) <= 2
+    assert int(rec.maps[steps].sum()) == int(fin.sum())
+    g = rec.final
+    assert np.max(np.abs(g["x"] - ref["x"])) <= 1e-9
+

@@ -9,11 +9,13 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "nbody_oracle.c")
 PINS = ["tests/test_oracle_accel.py", "tests/test_oracle_halo.py",
-        "tests/test_oracle_integrators.py", "tests/test_oracle_diag.py"]
+        "tests/test_oracle_integrators.py", "tests/test_oracle_diag.py", "tests/test_oracle_density.py",
+        "tests/test_oracle_hermite.py"]
 
 # (name, original text, planted mistake); each original occurs in the source
 MUTATIONS = [
-    ("softening dropped", "const double d2 = eps * eps;\n    double ax", "const double d2 = 0.0 * eps;\n    double ax"),
+    ("softening dropped", "const double d2 = eps * eps;\n    double ax = 0.0", "const double d2 = 0.0 * eps;\n    double ax = 0.0"),
+    ("jerk softening dropped", "const double d2 = eps * eps;\n    double ax = 0, ay", "const double d2 = 0.0 * eps;\n    double ax = 0, ay"),
     ("attraction sign", "ax -= s * dx;", "ax += s * dx;"),
     ("source mass index", "const double s = G * m[j] / r3;", "const double s = G * m[i] / r3;"),
     ("distance power", "const double r3 = r2 * r;", "const double r3 = r2;"),
@@ -29,6 +31,18 @@ MUTATIONS = [
     ("halo field power", "return v2 * (1.0 - atan(s) / s) / (r * r);", "return v2 * (1.0 - atan(s) / s) / r;"),
     ("halo potential log factor", "return v2 * (atan_over_s + 0.5 * log1p(s * s));", "return v2 * (atan_over_s + log1p(s * s));"),
     ("halo core series", "sum += ((k % 2) ? term : -term) / (2.0 * k + 1.0);", "sum += term / (2.0 * k + 1.0);"),
+    ("jerk radial term sign", "jx += G * m[j] * (ux / R3 - 3.0 * rv * rx / R5);", "jx += G * m[j] * (ux / R3 + 3.0 * rv * rx / R5);"),
+    ("jerk relative velocity", "const double ux = vx[j] - vx[i], uy", "const double ux = vx[j] + vx[i], uy"),
+    ("halo jerk radial term dropped", "o[3] -= g * vx[i] + hh * rv * x[i];", "o[3] -= g * vx[i];"),
+    ("halo jerk series sign", "sum += ((k % 2) ? term : -term) * (2.0 * k - 2.0) / (2.0 * k + 1.0);", "sum += term * (2.0 * k - 2.0) / (2.0 * k + 1.0);"),
+    ("hermite position corrector", "x[i] += (vx[i] + wx) * dt / 2.0 + (ax[i] - bx[i]) * dt * dt / 12.0;", "x[i] += (vx[i] + wx) * dt / 2.0;"),
+    ("hermite velocity corrector", "const double wy = vy[i] + (ay[i] + by[i]) * dt / 2.0 + (jy[i] - ky[i]) * dt * dt / 12.0;", "const double wy = vy[i] + (ay[i] + by[i]) * dt / 2.0 + (jy[i] - ky[i]) * dt * dt / 6.0;"),
+    ("hermite predictor without jerk", "py[i] = y[i] + vy[i] * dt + ay[i] * dt * dt / 2.0 + jy[i] * dt * dt * dt / 6.0;", "py[i] = y[i] + vy[i] * dt + ay[i] * dt * dt / 2.0;"),
+    ("rk4 weight", "y[i] += dt / 6.0 * (k1ry[i] + 2.0 * k2ry[i] + 2.0 * k3ry[i] + k4ry[i]);", "y[i] += dt / 6.0 * (k1ry[i] + 2.0 * k2ry[i] + k3ry[i] + 2.0 * k4ry[i]);"),
+    ("rk4 last stage", "sy[i] = y[i] + dt * k3ry[i];", "sy[i] = y[i] + dt / 2.0 * k3ry[i];"),
+    ("density map transposed", "counts[(int64_t)fy * nx + (int64_t)fx] += 1u;", "counts[(int64_t)fx * ny + (int64_t)fy] += 1u;"),
+    ("density right edge kept", "fx < (double)nx && fy", "fx <= (double)nx && fy"),
+    ("density cell scale", "const double fy = floor((y[i] - y0) * sy);", "const double fy = floor((y[i] - y0) * sx);"),
     ("halo series branch point", "if (s < 0.5) return v2 / (rc * rc) * halo_series_over_s2(s);", "if (s < 0.5) return v2 / (rc * rc) / 3.0;"),
 ]
 

@@ -11,7 +11,8 @@ Workloads (all in G = 1 units, equal particle masses m = M/N):
 * ``exp_disk``  -- the gravitationally unstable exponential stellar disk used
   for the paper's galactic-disk runs (Section 3): surface density
   ~ exp(-R/h) cut at R = 4h, vertical sech^2(z/z0), rotation set by the
-  enclosed mass of disk plus a fixed cored isothermal halo, radial dispersion
+  enclosed mass of disk plus a fixed cored isothermal halo (or of the disk
+  alone with ``halo=no_halo()``, the paper's self-gravitating case), radial dispersion
   from a Toomre Q, azimuthal dispersion from the epicyclic ratio and mean
   rotation from the radial Jeans (asymmetric-drift) balance of Eq. (3).
   The paper builds its disks with an iterative equilibrium method that it
@@ -51,6 +52,22 @@ def default_halo(h: float = 1.0, md: float = 1.0, G: float = 1.0) -> HaloSpec:
     rc = h
     v2 = G * md / (4.0 * h - rc * math.atan(4.0 * h / rc))
     return HaloSpec(v2=v2, rc=rc)
+
+
+def no_halo() -> HaloSpec:
+    """No external field: the completely self-gravitating disk of the paper's
+    Section 2, whose rotation comes from the disk's own enclosed mass."""
+    return HaloSpec(v2=0.0, rc=1.0)
+
+
+def outer_period(h: float = 1.0, rmax_h: float = 4.0, md: float = 1.0, halo: HaloSpec | None = None,
+                 G: float = 1.0) -> float:
+    """Rotation period 2 pi R / v_c(R) at the disk's edge R = rmax_h h, with
+    v_c^2 = G M(<R) / R as in exp_disk (the disk's whole mass is inside)."""
+    halo = default_halo(h, md, G) if halo is None else halo
+    R = rmax_h * h
+    m = md + (halo.v2 / G) * (R - halo.rc * math.atan(R / halo.rc))
+    return 2.0 * math.pi * R / math.sqrt(G * m / R)
 
 
 def _com_frame(d: dict) -> dict:
@@ -280,4 +297,6 @@ def make(kind: str, n: int, seed: int) -> dict:
         return plummer(n, seed)
     if kind == "disk":
         return exp_disk(n, seed)
+    if kind == "disk_sg":
+        return exp_disk(n, seed, halo=no_halo())
     raise ValueError(f"unknown workload {kind!r}")
