@@ -190,6 +190,43 @@ NBODY_API nbody_status nbody_step_kdk(nbody_ctx *ctx, nbody_sys *sys, const nbod
 NBODY_API nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
                            int64_t nsteps, void *stream);
 
+/* Acceleration and jerk.  The abstract names fourth-order schemes without
+ * fixing one; the fourth-order Hermite scheme (Makino & Aarseth 1992) needs
+ * the time derivative of Eq. (1)'s acceleration along the motion,
+ *   j_i = G sum_{j != i} m_j [u - 3 (r . u) r / R^2] / R^3,
+ * r = r_j - r_i, u = v_j - v_i, R^2 = |r|^2 + eps^2 (plus the halo's jerk
+ * -g v - (g'(r)/r)(r . v) r when prm->halo).  Overwrites sys->ax/ay/az and
+ * the caller-owned DEVICE arrays jx, jy, jz (n doubles each) with a and j at
+ * the current positions and velocities.  sys->phi is not written.  Float64
+ * error as nbody_accel's; mixed and float32 as their acceleration paths. */
+NBODY_API nbody_status nbody_accel_jerk(nbody_ctx *ctx, const nbody_sys *sys, double *jx, double *jy,
+                                        double *jz, const nbody_params *prm, void *stream);
+
+/* nsteps fourth-order Hermite steps of size dt, one acceleration-and-jerk
+ * sum each:  predict r_p = r + v dt + a dt^2/2 + j dt^3/6,
+ * v_p = v + a dt + j dt^2/2;  evaluate a1, j1 at (r_p, v_p);  correct
+ *   v' = v + (a + a1) dt/2 + (j - j1) dt^2/12,
+ *   r' = r + (v + v') dt/2 + (a - a1) dt^2/12;   a, j <- a1, j1.
+ * Precondition: a and j hold the values at the current state (call
+ * nbody_accel_jerk once first); on return they hold those of the last
+ * predicted state, as the scheme carries them.  Updates x, y, z, vx, vy, vz,
+ * ax, ay, az, jx, jy, jz.  Scratch: 6 n doubles held by the context. */
+NBODY_API nbody_status nbody_step_hermite(nbody_ctx *ctx, nbody_sys *sys, double *jx, double *jy, double *jz,
+                                          const nbody_params *prm, double dt, int64_t nsteps, void *stream);
+
+/* nsteps classical fourth-order Runge-Kutta steps of the first-order
+ * system r' = v, v' = a(r) (Section 1 contrasts the leapfrog's single force
+ * evaluation per step with Runge-Kutta schemes):  with a1 = a(r),
+ *   a2 = a(r + dt/2 v),  a3 = a(r + dt/2 (v + dt/2 a1)),
+ *   a4 = a(r + dt (v + dt/2 a2)),
+ *   r' = r + dt/6 (v + 2 (v + dt/2 a1) + 2 (v + dt/2 a2) + (v + dt a3)),
+ *   v' = v + dt/6 (a1 + 2 a2 + 2 a3 + a4),
+ * then a(r') is evaluated: four force evaluations per step.  Same
+ * precondition and postcondition as nbody_step_kdk.  Scratch: 12 n doubles
+ * held by the context. */
+NBODY_API nbody_status nbody_step_rk4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt,
+                                      int64_t nsteps, void *stream);
+
 /* Eqs. (8)-(10): write one nbody_diag_t to DEVICE memory out_dev.  Costs an
  * O(N^2) float64 potential pass plus O(N) reductions in a fixed order, so
  * the result is deterministic for a given n.  Does not modify sys. */

@@ -82,7 +82,7 @@ def _load(path: str | None = None):
                                     _dbl, _i64, _dbl, _dbl, _int, _int]
         lib.orc_diag.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _D, _int]
         lib.orc_accel_jerk.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _D, _D, _D, _D,
-                                       _D, _D, _int]
+                                       _D, _D, _D, _D, _int]
         lib.orc_step_hermite.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl,
                                          _dbl, hp, _dbl, _i64, _int]
         lib.orc_step_rk4.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _dbl,
@@ -240,16 +240,18 @@ def diag(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0) -> dict:
     return dict(zip(DIAG_KEYS, out.tolist()))
 
 
-def accel_jerk(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0):
+def accel_jerk(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0, want_scale=False):
     """Acceleration (Eqs. (1)-(2)) and its time derivative along the motion,
-    plus the halo's when given.  Returns (ax, ay, az, jx, jy, jz)."""
+    plus the halo's when given.  Returns (ax, ay, az, jx, jy, jz), and with
+    want_scale also the sums of the self-gravity terms' magnitudes (A, J)."""
     lib = _load()
     a = {k: _f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
     n = a["x"].size
-    out = [np.zeros(n) for _ in range(6)]
+    out = [np.zeros(n) for _ in range(8 if want_scale else 6)]
     hp, _keep = _halo(halo)
+    sc = [_p(o) for o in out[6:]] if want_scale else [None, None]
     lib.orc_accel_jerk(n, *[_p(a[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], G, eps, hp,
-                       *[_p(o) for o in out], nthreads)
+                       *[_p(o) for o in out[:6]], *sc, nthreads)
     return tuple(out)
 
 

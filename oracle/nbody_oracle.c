@@ -268,11 +268,13 @@ static double halo_h(double s) {
     return 1.0 / (s2 * (1.0 + s2)) - 3.0 / (s2 * s2) + 3.0 * atan(s) / (s2 * s2 * s);
 }
 
+/* o[0..5] = a, j of particle i; o[6] = sum |a term|, o[7] = sum of the
+ * jerk terms' magnitude bounds G m_j (|u| / R^3 + 3 |r . u| |r| / R^5). */
 static void jerk_one(int64_t n, const double *x, const double *y, const double *z,
                      const double *vx, const double *vy, const double *vz, const double *m,
                      double G, double eps, int64_t i, double *o) {
     const double d2 = eps * eps;
-    double ax = 0, ay = 0, az = 0, jx = 0, jy = 0, jz = 0;
+    double ax = 0, ay = 0, az = 0, jx = 0, jy = 0, jz = 0, sa = 0, sj = 0;
     for (int64_t j = 0; j < n; ++j) {
         if (j == i) continue;
         const double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
@@ -289,19 +291,24 @@ static void jerk_one(int64_t n, const double *x, const double *y, const double *
         jx += G * m[j] * (ux / R3 - 3.0 * rv * rx / R5);
         jy += G * m[j] * (uy / R3 - 3.0 * rv * ry / R5);
         jz += G * m[j] * (uz / R3 - 3.0 * rv * rz / R5);
+        const double rl = sqrt(rx * rx + ry * ry + rz * rz);
+        sa += G * m[j] * rl / R3;
+        sj += G * m[j] * (sqrt(ux * ux + uy * uy + uz * uz) / R3 + 3.0 * fabs(rv) * rl / R5);
     }
-    o[0] = ax; o[1] = ay; o[2] = az; o[3] = jx; o[4] = jy; o[5] = jz;
+    o[0] = ax; o[1] = ay; o[2] = az; o[3] = jx; o[4] = jy; o[5] = jz; o[6] = sa; o[7] = sj;
 }
 
-/* acceleration and jerk of every particle (plus the halo's when h->on) */
+/* acceleration and jerk of every particle (plus the halo's when h->on);
+ * sa, sj (nullable): the sums of the self-gravity terms' magnitudes, scales
+ * for conditioned error measures. */
 void orc_accel_jerk(int64_t n, const double *x, const double *y, const double *z, const double *vx,
                     const double *vy, const double *vz, const double *m, double G, double eps,
                     const orc_halo *h, double *ax, double *ay, double *az, double *jx, double *jy,
-                    double *jz, int nthreads) {
+                    double *jz, double *sa, double *sj, int nthreads) {
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
-        double o[6];
+        double o[8];
         jerk_one(n, x, y, z, vx, vy, vz, m, G, eps, i, o);
         if (h && h->on) {
             const double r = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
@@ -316,6 +323,8 @@ void orc_accel_jerk(int64_t n, const double *x, const double *y, const double *z
             o[5] -= g * vz[i] + hh * rv * z[i];
         }
         ax[i] = o[0]; ay[i] = o[1]; az[i] = o[2]; jx[i] = o[3]; jy[i] = o[4]; jz[i] = o[5];
+        if (sa) sa[i] = o[6];
+        if (sj) sj[i] = o[7];
     }
 }
 
@@ -344,7 +353,8 @@ void orc_step_hermite(int64_t n, double *x, double *y, double *z, double *vx, do
             pvy[i] = vy[i] + ay[i] * dt + jy[i] * dt * dt / 2.0;
             pvz[i] = vz[i] + az[i] * dt + jz[i] * dt * dt / 2.0;
         }
-        orc_accel_jerk(n, px, py, pz, pvx, pvy, pvz, m, G, eps, h, bx, by, bz, kx, ky, kz, nthreads);
+        orc_accel_jerk(n, px, py, pz, pvx, pvy, pvz, m, G, eps, h, bx, by, bz, kx, ky, kz, NULL, NULL,
+                       nthreads);
         ++g_force_evals;
         for (int64_t i = 0; i < n; ++i) {
             const double wx = vx[i] + (ax[i] + bx[i]) * dt / 2.0 + (jx[i] - kx[i]) * dt * dt / 12.0;

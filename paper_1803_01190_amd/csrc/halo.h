@@ -27,6 +27,27 @@ __device__ __forceinline__ double halo_g_over_r3(double r2, double v2, double rc
     return v2 * (1.0 - atan(s) / s) / r2;
 }
 
+// g'(r) / r, with g = G M(<r) / r^3, for the halo's jerk j_h = -g v - (g'/r)(r.v) r.
+// With F(s) = (1 - atan(s)/s) / s^2 (g = V^2 F / rc^2), g'/r = V^2 H(s) / rc^4
+// where H(s) = F'(s)/s = 1/(s^2 (1 + s^2)) - 3/s^4 + 3 atan(s)/s^5; below
+// s = 1/2 the sum sum_{m>=0} (-1)^{m+1} (2m+2)/(2m+5) s^{2m} (Horner, 28 terms).
+__device__ __forceinline__ double halo_dg_over_r(double r2, double v2, double rc) {
+    const double rc2 = rc * rc;
+    const double s2 = r2 / rc2;
+    double h;
+    if (s2 < 0.25) {
+        h = 0.0;
+#pragma unroll
+        for (int m = 27; m >= 0; --m)
+            h = __builtin_fma(h, s2, ((m & 1) ? 1.0 : -1.0) * (2.0 * m + 2.0) / (2.0 * m + 5.0));
+    } else {
+        const double s = sqrt(s2);
+        const double s4 = s2 * s2;
+        h = 1.0 / (s2 * (1.0 + s2)) - 3.0 / s4 + 3.0 * atan(s) / (s4 * s);
+    }
+    return v2 * h / (rc2 * rc2);
+}
+
 __device__ __forceinline__ double halo_potential(double r2, double v2, double rc) {
     const double s2 = r2 / (rc * rc);
     const double s = sqrt(s2);

@@ -1,0 +1,304 @@
+// Acceleration and jerk in one pair pass, for the fourth-order Hermite
+// scheme (Makino & Aarseth 1992), one reading of the fourth-order schemes the
+// paper's abstract names.  The jerk is the time derivative of Eq. (1)'s
+// acceleration along the motion; with r = r_j - r_i, u = v_j - v_i and the
+// softened R^2 = |r|^2 + eps^2,
+//   a_i += G m_j r / R^3,
+//   j_i += G m_j [u - 3 (r . u) r / R^2] / R^3.
+// Same structure as the acceleration kernel (accel.hip): BLOCK lanes, R
+// targets per lane in registers, source tiles of BLOCK particles staged in
+// LDS and read back as wave-wide broadcasts, optional source split with a
+// fixed-order reduction.  Float64: v_rsq_f64 with the first-order correction
+// of y^3 (1 - 3e/2, e = R^2 y^2 - 1) and 1/R^2 = y^2 (1 - e) (relative error
+// e^2 < 1.1e-14).  Mixed: separations and relative velocities formed in
+// float64 and rounded to float32, float32 pair terms summed per tile and
+// added into float64.  Float32: everything in float32, one running sum.
+//
+// The epilogue either stores a and j, or (Hermite step) applies the
+// corrector to the particle's own current state:
+//   v' = v + (a + a1) dt/2 + (j - j1) dt^2/12,
+//   r' = r + (v + v') dt/2 + (a - a1) dt^2/12,   a, j <- a1, j1.
+#include <type_traits>
+
+#include "nbody_internal.h"
+#include "halo.h"
+
+namespace nb {
+namespace {
+
+struct alignas(16) SD { double x, y, z, u, v, w, m, pad; };
+struct alignas(16) SF { float x, y, z, u, v, w, m, pad; };
+
+template <int PREC> struct JT;
+template <> struct JT<P_FP64> { using S = SD; using Ti = double; using A = double; };
+template <> struct JT<P_MIXED> { using S = SD; using Ti = double; using A = float; };
+template <> struct JT<P_FP32> { using S = SF; using Ti = float; using A = float; };
+
+template <int PREC, int R>
+struct JLane {
+    using Ti = typename JT<PREC>::Ti;
+    using A = typename JT<PREC>::A;
+    Ti x[R], y[R], z[R], u[R], v[R], w[R];
+    A ax[R], ay[R], az[R], jx[R], jy[R], jz[R];   // inner sums
+    double oax[R], oay[R], oaz[R], ojx[R], ojy[R], ojz[R];  // outer sums (mixed)
+    double km15, km3;
+};
+
+template <class T>
+__device__ __forceinline__ T pin_vgpr(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+template <int PREC>
+__device__ __forceinline__ typename JT<PREC>::S load_src(const JerkLaunch &J, int64_t j, bool ok) {
+    typename JT<PREC>::S e;
+    using T = decltype(e.x);
+    e.x = ok ? (T)J.x[j] : T(0); e.y = ok ? (T)J.y[j] : T(0); e.z = ok ? (T)J.z[j] : T(0);
+    e.u = ok ? (T)J.vx[j] : T(0); e.v = ok ? (T)J.vy[j] : T(0); e.w = ok ? (T)J.vz[j] : T(0);
+    e.m = ok ? (T)J.m[j] : T(0); e.pad = T(0);
+    return e;
+}
+
+template <int PREC, int R, bool SAFE>
+__device__ __forceinline__ void interact(JLane<PREC, R> &L, const typename JT<PREC>::S &s, double eps2,
+                                         float eps2f) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (PREC == P_FP64) {
+            const double dx = s.x - L.x[r], dy = s.y - L.y[r], dz = s.z - L.z[r];
+            const double du = s.u - L.u[r], dv = s.v - L.v[r], dw = s.w - L.w[r];
+            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+            double y = __builtin_amdgcn_rsq(r2);
+            if constexpr (SAFE) y = (r2 > 0.0) ? y : 0.0;
+            const double y2 = y * y;
+            const double e = __builtin_fma(r2, y2, -1.0);
+            const double c3 = __builtin_fma(L.km15, e, 1.0);
+            const double sm = ((s.m * y) * y2) * c3;
+            const double q = __builtin_fma(-e, y2, y2);
+            const double rv = __builtin_fma(dx, du, __builtin_fma(dy, dv, dz * dw));
+            const double t = (L.km3 * rv) * q;
+            L.ax[r] = __builtin_fma(sm, dx, L.ax[r]);
+            L.ay[r] = __builtin_fma(sm, dy, L.ay[r]);
+            L.az[r] = __builtin_fma(sm, dz, L.az[r]);
+            L.jx[r] = __builtin_fma(sm, __builtin_fma(t, dx, du), L.jx[r]);
+            L.jy[r] = __builtin_fma(sm, __builtin_fma(t, dy, dv), L.jy[r]);
+            L.jz[r] = __builtin_fma(sm, __builtin_fma(t, dz, dw), L.jz[r]);
+        } else {
+            float dx, dy, dz, du, dv, dw, m;
+            if constexpr (PREC == P_MIXED) {
+                dx = (float)(s.x - L.x[r]); dy = (float)(s.y - L.y[r]); dz = (float)(s.z - L.z[r]);
+                du = (float)(s.u - L.u[r]); dv = (float)(s.v - L.v[r]); dw = (float)(s.w - L.w[r]);
+                m = (float)s.m;
+            } else {
+                dx = s.x - L.x[r]; dy = s.y - L.y[r]; dz = s.z - L.z[r];
+                du = s.u - L.u[r]; dv = s.v - L.v[r]; dw = s.w - L.w[r];
+                m = s.m;
+            }
+            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+            float y = __builtin_amdgcn_rsqf(r2);
+            if constexpr (SAFE) y = (r2 > 0.0f) ? y : 0.0f;
+            const float y2 = y * y;
+            const float sm = (m * y) * y2;
+            const float rv = __builtin_fmaf(dx, du, __builtin_fmaf(dy, dv, dz * dw));
+            const float t = (-3.0f * rv) * y2;
+            L.ax[r] = __builtin_fmaf(sm, dx, L.ax[r]);
+            L.ay[r] = __builtin_fmaf(sm, dy, L.ay[r]);
+            L.az[r] = __builtin_fmaf(sm, dz, L.az[r]);
+            L.jx[r] = __builtin_fmaf(sm, __builtin_fmaf(t, dx, du), L.jx[r]);
+            L.jy[r] = __builtin_fmaf(sm, __builtin_fmaf(t, dy, dv), L.jy[r]);
+            L.jz[r] = __builtin_fmaf(sm, __builtin_fmaf(t, dz, dw), L.jz[r]);
+        }
+    }
+}
+
+template <int PREC, int R>
+__device__ __forceinline__ void flush(JLane<PREC, R> &L) {
+    if constexpr (PREC == P_MIXED) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            L.oax[r] += (double)L.ax[r]; L.oay[r] += (double)L.ay[r]; L.oaz[r] += (double)L.az[r];
+            L.ojx[r] += (double)L.jx[r]; L.ojy[r] += (double)L.jy[r]; L.ojz[r] += (double)L.jz[r];
+            L.ax[r] = L.ay[r] = L.az[r] = L.jx[r] = L.jy[r] = L.jz[r] = 0.0f;
+        }
+    }
+}
+
+// The six raw sums of target slot r.
+template <int PREC, int R>
+__device__ __forceinline__ void raw(const JLane<PREC, R> &L, int r, double *o) {
+    if constexpr (PREC == P_MIXED) {
+        o[0] = L.oax[r]; o[1] = L.oay[r]; o[2] = L.oaz[r]; o[3] = L.ojx[r]; o[4] = L.ojy[r]; o[5] = L.ojz[r];
+    } else {
+        o[0] = L.ax[r]; o[1] = L.ay[r]; o[2] = L.az[r]; o[3] = L.jx[r]; o[4] = L.jy[r]; o[5] = L.jz[r];
+    }
+}
+
+// Halo field and its jerk at (x, v):  a_h = -g x,  j_h = -g v - h (x . v) x,
+// g = G M(<r)/r^3, h = g'(r)/r.
+__device__ __forceinline__ void halo_aj(const SysConst &sc, const double *p, const double *v, double *o) {
+    const double r2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    const double g = halo_g_over_r3(r2, sc.halo_v2, sc.halo_rc);
+    const double h = halo_dg_over_r(r2, sc.halo_v2, sc.halo_rc);
+    const double rv = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o[c] = __builtin_fma(-g, p[c], o[c]);
+        o[3 + c] = o[3 + c] - __builtin_fma(g, v[c], h * rv * p[c]);
+    }
+}
+
+// Final a, j of target i from its raw sums, then either store them or apply
+// the Hermite corrector.
+template <int PREC>
+__device__ __forceinline__ void finish(const JerkLaunch &J, int64_t i, const double *sums) {
+    double o[6];
+    if constexpr (PREC == P_FP32) {
+        const float g = (float)J.sc.G;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = g * (float)sums[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = J.sc.G * sums[c];
+    }
+    if (J.sc.halo) {
+        const double p[3] = {J.x[i], J.y[i], J.z[i]};
+        const double v[3] = {J.vx[i], J.vy[i], J.vz[i]};
+        halo_aj(J.sc, p, v, o);
+        if constexpr (PREC == P_FP32) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) o[c] = (float)o[c];
+        }
+    }
+    if (!J.corr) {
+        J.ax[i] = o[0]; J.ay[i] = o[1]; J.az[i] = o[2];
+        J.jx[i] = o[3]; J.jy[i] = o[4]; J.jz[i] = o[5];
+        return;
+    }
+    double *const X[3] = {J.x0, J.y0, J.z0};
+    double *const V[3] = {J.vx0, J.vy0, J.vz0};
+    double *const Aa[3] = {J.ax, J.ay, J.az};
+    double *const Jj[3] = {J.jx, J.jy, J.jz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (PREC == P_FP32) {
+            const float dt = (float)J.dt, h = 0.5f * dt, k = dt * dt / 12.0f;
+            const float a0 = (float)Aa[c][i], j0 = (float)Jj[c][i], v0 = (float)V[c][i];
+            const float a1 = (float)o[c], j1 = (float)o[3 + c];
+            const float v1 = v0 + (a0 + a1) * h + (j0 - j1) * k;
+            X[c][i] = (float)X[c][i] + (v0 + v1) * h + (a0 - a1) * k;
+            V[c][i] = v1;
+        } else {
+            const double dt = J.dt, h = 0.5 * dt, k = dt * dt / 12.0;
+            const double a0 = Aa[c][i], j0 = Jj[c][i], v0 = V[c][i];
+            const double a1 = o[c], j1 = o[3 + c];
+            const double v1 = v0 + (a0 + a1) * h + (j0 - j1) * k;
+            X[c][i] = X[c][i] + (v0 + v1) * h + (a0 - a1) * k;
+            V[c][i] = v1;
+        }
+        Aa[c][i] = o[c];
+        Jj[c][i] = o[3 + c];
+    }
+}
+
+template <int PREC, int R, int BLOCK, bool SAFE>
+__global__ __launch_bounds__(BLOCK) void k_pair_jerk(JerkLaunch J, int64_t chunk) {
+    __shared__ typename JT<PREC>::S tile[BLOCK];
+    const int64_t ib = J.i0 + (int64_t)blockIdx.x * (BLOCK * R);
+    const int64_t jb = (int64_t)blockIdx.y * chunk;
+    const int64_t je = (jb + chunk < J.sc.n) ? jb + chunk : J.sc.n;
+    const int t = threadIdx.x;
+    JLane<PREC, R> L;
+    L.km15 = pin_vgpr(-1.5);
+    L.km3 = pin_vgpr(-3.0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = ib + (int64_t)r * BLOCK + t;
+        const bool ok = i < J.i1;
+        using Ti = typename JT<PREC>::Ti;
+        L.x[r] = ok ? (Ti)J.x[i] : Ti(0); L.y[r] = ok ? (Ti)J.y[i] : Ti(0); L.z[r] = ok ? (Ti)J.z[i] : Ti(0);
+        L.u[r] = ok ? (Ti)J.vx[i] : Ti(0); L.v[r] = ok ? (Ti)J.vy[i] : Ti(0); L.w[r] = ok ? (Ti)J.vz[i] : Ti(0);
+        L.ax[r] = L.ay[r] = L.az[r] = L.jx[r] = L.jy[r] = L.jz[r] = 0;
+        L.oax[r] = L.oay[r] = L.oaz[r] = L.ojx[r] = L.ojy[r] = L.ojz[r] = 0.0;
+    }
+    for (int64_t jt = jb; jt < je; jt += BLOCK) {
+        const int64_t j = jt + t;
+        tile[t] = load_src<PREC>(J, j, j < je);
+        __syncthreads();
+#pragma unroll 2
+        for (int k = 0; k < BLOCK; ++k) interact<PREC, R, SAFE>(L, tile[k], J.sc.eps2, J.sc.eps2f);
+        flush(L);
+        __syncthreads();
+    }
+    const int64_t rows = J.i1 - J.i0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = ib + (int64_t)r * BLOCK + t;
+        if (i >= J.i1) continue;
+        double o[6];
+        raw<PREC, R>(L, r, o);
+        if (J.split > 1) {
+            double *q = J.part + (int64_t)blockIdx.y * 6 * rows + (i - J.i0);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c * rows] = o[c];
+        } else {
+            finish<PREC>(J, i, o);
+        }
+    }
+}
+
+// Fixed-order reduction of the split partial sums, then the epilogue.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_pair_jerk_reduce(JerkLaunch J) {
+    const int64_t rows = J.i1 - J.i0;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= rows) return;
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < J.split; ++s) {
+        const double *b = J.part + (int64_t)s * 6 * rows + q;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] += b[c * rows];
+    }
+    finish<PREC>(J, J.i0 + q, o);
+}
+
+template <int PREC, int R>
+hipError_t go(const JerkLaunch &J, hipStream_t s) {
+    const int64_t rows = J.i1 - J.i0;
+    const int64_t per = 256LL * R;
+    const int64_t nbx = (rows + per - 1) / per;
+    if (nbx <= 0) return hipSuccess;
+    const int64_t per_chunk = (J.sc.n + J.split - 1) / J.split;
+    const int64_t chunk = ((per_chunk + 255) / 256) * 256;
+    dim3 grid((unsigned)nbx, (unsigned)J.split);
+    const bool safe = (PREC == P_FP64) ? J.sc.safe64 : J.sc.safe32;
+    if (safe)
+        hipLaunchKernelGGL((k_pair_jerk<PREC, R, 256, true>), grid, dim3(256), 0, s, J, chunk);
+    else
+        hipLaunchKernelGGL((k_pair_jerk<PREC, R, 256, false>), grid, dim3(256), 0, s, J, chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || J.split <= 1) return e;
+    hipLaunchKernelGGL(k_pair_jerk_reduce<PREC>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, J);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t pick(const JerkLaunch &J, hipStream_t s) {
+    if (J.R == 2) return go<PREC, 2>(J, s);
+    if (J.R == 1) return go<PREC, 1>(J, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_pair_jerk(const JerkLaunch &J, hipStream_t s) {
+    if (J.block != 256 || J.split < 1) return hipErrorInvalidValue;
+    switch (J.sc.prec) {
+        case P_FP64: return pick<P_FP64>(J, s);
+        case P_MIXED: return pick<P_MIXED>(J, s);
+        case P_FP32: return J.split == 1 ? pick<P_FP32>(J, s) : hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nb

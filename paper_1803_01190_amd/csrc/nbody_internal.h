@@ -92,6 +92,42 @@ hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst
                               int32_t B, double *out, hipStream_t s);
 
 // Small utilities.
+// Acceleration and jerk pair sum (fourth-order Hermite).  The sum is
+// evaluated at (x, v); without corr it stores a and j, with corr it applies
+// the Hermite corrector to the current state (x0, v0, and a, j as a0, j0)
+// and leaves a1, j1 in a, j.
+struct JerkLaunch {
+    const double *x, *y, *z, *vx, *vy, *vz, *m;
+    double *ax, *ay, *az, *jx, *jy, *jz;
+    double *x0, *y0, *z0, *vx0, *vy0, *vz0;
+    SysConst sc;
+    int64_t i0, i1;
+    int R, block, split, corr;
+    double dt;
+    double *part;   // split partial sums: split * 6 * (i1 - i0) doubles
+};
+
+struct HermitePredict {
+    const double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az, *jx, *jy, *jz;
+    double *xp, *yp, *zp, *vxp, *vyp, *vzp;
+    int64_t n;
+    double dt;
+};
+
+// Classical RK4 stage pass: stage 1-3 write stage positions s, stage 4 the
+// final update of st (a1 is st's acceleration).
+struct RK4Launch {
+    State st;
+    double *s[3];
+    const double *a2[3], *a3[3], *a4[3];
+    int64_t n;
+    double dt;
+    int stage;
+};
+
+hipError_t launch_pair_jerk(const JerkLaunch &J, hipStream_t s);
+hipError_t launch_hermite_predict(const HermitePredict &H, int fp32, hipStream_t s);
+hipError_t launch_rk4(const RK4Launch &K, int fp32, hipStream_t s);
 hipError_t launch_surface_density(const double *x, const double *y, int64_t n, int32_t nx, int32_t ny,
                                   double x0, double y0, double sx, double sy, uint32_t *counts,
                                   hipStream_t s);

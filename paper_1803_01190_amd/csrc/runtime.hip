@@ -6,7 +6,10 @@
 //   KDK leapfrog, Section 1, Eqs. (5)-(7), in half-kick form, one force
 //   evaluation per step:  kick_drift(dt) ; pair sum with fused closing kick.
 //   Fourth order (named in the abstract, unspecified): triple jump
-//   KDK(w1 dt) KDK(w0 dt) KDK(w1 dt), w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1.
+//   KDK(w1 dt) KDK(w0 dt) KDK(w1 dt), w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1;
+//   the fourth-order Hermite scheme (predict, one acceleration-and-jerk sum
+//   with the corrector fused into its epilogue); classical RK4 (four
+//   acceleration sums per step, Section 1's Runge-Kutta comparison).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +37,8 @@ struct nbody_ctx {
     size_t part_cap = 0;   // doubles
     double *phi = nullptr;
     size_t phi_cap = 0;    // doubles
+    double *integ = nullptr;  // Hermite predicted state / RK4 stages
+    size_t integ_cap = 0;     // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
     // Scratch outgrown by a larger call is kept (not freed) until the
     // context is destroyed: a HIP graph captured earlier may still use it,
@@ -374,6 +379,43 @@ nbody_status batch_steps(nbody_ctx *ctx, nbody_batch *b, const nbody_sys *all, i
     return NB_OK;
 }
 
+// Launch plan of the acceleration-and-jerk sum: 256 lanes, LDS tiles, two
+// targets per lane when there are enough workgroups, sources split until the
+// chip has two workgroups per CU (never for float32, as for the acceleration).
+nbody_plan jerk_plan(const nbody_ctx *ctx, int prec, int64_t n) {
+    nbody_plan p{2, 256, 1, 0};
+    const int64_t want = 2LL * ctx->cus;
+    if ((n + 511) / 512 < want) p.R = 1;
+    if (prec == P_FP32) return p;
+    const int64_t nblk = (n + 256LL * p.R - 1) / (256LL * p.R);
+    while (nblk * p.split < want && n / (2LL * p.split) >= 512 && p.split < 64) p.split *= 2;
+    return p;
+}
+
+nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, hipStream_t s) {
+    const int64_t rows = J.i1 - J.i0;
+    if (rows <= 0) return NB_OK;
+    const nbody_plan pl = jerk_plan(ctx, J.sc.prec, J.sc.n);
+    J.R = pl.R;
+    J.block = pl.block;
+    J.split = pl.split;
+    if (J.split > 1) {
+        nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, (size_t)J.split * 6 * (size_t)rows);
+        if (r != NB_OK) return r;
+        J.part = ctx->part;
+    }
+    Timed t(ctx, s, 0, rows * J.sc.n);
+    const hipError_t e = launch_pair_jerk(J, s);
+    if (e != hipSuccess) return hipfail(ctx, e, "acceleration-and-jerk launch");
+    return NB_OK;
+}
+
+nbody_status check_jerk(nbody_ctx *ctx, const nbody_sys *sys, const double *jx, const double *jy,
+                        const double *jz) {
+    if (sys->n > 0 && (!jx || !jy || !jz)) return fail(ctx, NB_EINVAL, "a jerk array is NULL");
+    return NB_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -414,6 +456,7 @@ nbody_status nbody_ctx_destroy(nbody_ctx *ctx) {
     for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->phi) (void)hipFree(ctx->phi);
+    if (ctx->integ) (void)hipFree(ctx->integ);
     for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->sysc) (void)hipFree(ctx->sysc);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -498,6 +541,146 @@ nbody_status nbody_step_kdk(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *
 nbody_status nbody_step_o4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt, int64_t nsteps,
                            void *stream) {
     return step_common(ctx, sys, prm, dt, nsteps, stream, true);
+}
+
+nbody_status nbody_accel_jerk(nbody_ctx *ctx, const nbody_sys *sys, double *jx, double *jy, double *jz,
+                              const nbody_params *prm, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, true);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r == NB_OK) r = check_jerk(ctx, sys, jx, jy, jz);
+        if (r != NB_OK || sys->n == 0) return r;
+        DevGuard g(ctx->device);
+        JerkLaunch J{};
+        J.x = sys->x; J.y = sys->y; J.z = sys->z;
+        J.vx = sys->vx; J.vy = sys->vy; J.vz = sys->vz;
+        J.m = sys->m;
+        J.ax = sys->ax; J.ay = sys->ay; J.az = sys->az;
+        J.jx = jx; J.jy = jy; J.jz = jz;
+        J.sc = make_sysconst(prm, 0, sys->n, 0.0);
+        J.i0 = 0;
+        J.i1 = sys->n;
+        return run_jerk(ctx, J, (hipStream_t)stream);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_jerk");
+    }
+}
+
+nbody_status nbody_step_hermite(nbody_ctx *ctx, nbody_sys *sys, double *jx, double *jy, double *jz,
+                                const nbody_params *prm, double dt, int64_t nsteps, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, true);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r == NB_OK) r = check_jerk(ctx, sys, jx, jy, jz);
+        if (r != NB_OK) return r;
+        if (!is_finite(dt)) return fail(ctx, NB_EINVAL, "dt must be finite");
+        if (nsteps < 0) return fail(ctx, NB_EINVAL, "nsteps must be >= 0");
+        const int64_t n = sys->n;
+        if (n == 0 || nsteps == 0) return NB_OK;
+        DevGuard g(ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        r = ensure(ctx, &ctx->integ, &ctx->integ_cap, 6 * (size_t)n);
+        if (r != NB_OK) return r;
+        double *p = ctx->integ;
+        HermitePredict H{};
+        H.x = sys->x; H.y = sys->y; H.z = sys->z; H.vx = sys->vx; H.vy = sys->vy; H.vz = sys->vz;
+        H.ax = sys->ax; H.ay = sys->ay; H.az = sys->az; H.jx = jx; H.jy = jy; H.jz = jz;
+        H.xp = p; H.yp = p + n; H.zp = p + 2 * n; H.vxp = p + 3 * n; H.vyp = p + 4 * n; H.vzp = p + 5 * n;
+        H.n = n;
+        H.dt = dt;
+        JerkLaunch J{};
+        J.x = H.xp; J.y = H.yp; J.z = H.zp; J.vx = H.vxp; J.vy = H.vyp; J.vz = H.vzp;
+        J.m = sys->m;
+        J.ax = sys->ax; J.ay = sys->ay; J.az = sys->az;
+        J.jx = jx; J.jy = jy; J.jz = jz;
+        J.x0 = sys->x; J.y0 = sys->y; J.z0 = sys->z; J.vx0 = sys->vx; J.vy0 = sys->vy; J.vz0 = sys->vz;
+        J.sc = make_sysconst(prm, 0, n, dt);
+        J.i0 = 0;
+        J.i1 = n;
+        J.corr = 1;
+        J.dt = dt;
+        const int fp32 = prm->prec == NB_FP32;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            {
+                Timed t(ctx, s, 1, 0);
+                const hipError_t e = launch_hermite_predict(H, fp32, s);
+                if (e != hipSuccess) return hipfail(ctx, e, "Hermite predictor launch");
+            }
+            r = run_jerk(ctx, J, s);
+            if (r != NB_OK) return r;
+        }
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_step_hermite");
+    }
+}
+
+nbody_status nbody_step_rk4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *prm, double dt, int64_t nsteps,
+                            void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, true);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK) return r;
+        if (!is_finite(dt)) return fail(ctx, NB_EINVAL, "dt must be finite");
+        if (nsteps < 0) return fail(ctx, NB_EINVAL, "nsteps must be >= 0");
+        const int64_t n = sys->n;
+        if (n == 0 || nsteps == 0) return NB_OK;
+        DevGuard g(ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        r = ensure(ctx, &ctx->integ, &ctx->integ_cap, 12 * (size_t)n);
+        if (r != NB_OK) return r;
+        double *p = ctx->integ;
+        const State st = make_state(sys);
+        RK4Launch K{};
+        K.st = st;
+        for (int c = 0; c < 3; ++c) {
+            K.s[c] = p + c * n;
+            K.a2[c] = p + (3 + c) * n;
+            K.a3[c] = p + (6 + c) * n;
+            K.a4[c] = p + (9 + c) * n;
+        }
+        K.n = n;
+        K.dt = dt;
+        const SysConst sc = make_sysconst(prm, 0, n, dt);
+        const nbody_plan pl = mode_plan(ctx, prm->prec, n, MODE_ACC);
+        const int fmode = sys->phi ? MODE_ACC_PHI : MODE_ACC;
+        const nbody_plan fpl = mode_plan(ctx, prm->prec, n, fmode);
+        const int fp32 = prm->prec == NB_FP32;
+        // stage k writes its positions into K.s, whose accelerations go to a2, a3, a4
+        double *const out[3][3] = {{p + 3 * n, p + 4 * n, p + 5 * n},
+                                   {p + 6 * n, p + 7 * n, p + 8 * n},
+                                   {p + 9 * n, p + 10 * n, p + 11 * n}};
+        for (int64_t k = 0; k < nsteps; ++k) {
+            for (int stage = 1; stage <= 3; ++stage) {
+                K.stage = stage;
+                {
+                    Timed t(ctx, s, 1, 0);
+                    const hipError_t e = launch_rk4(K, fp32, s);
+                    if (e != hipSuccess) return hipfail(ctx, e, "RK4 stage launch");
+                }
+                State ss{};
+                ss.x = K.s[0]; ss.y = K.s[1]; ss.z = K.s[2];
+                ss.m = sys->m;
+                ss.ax = out[stage - 1][0]; ss.ay = out[stage - 1][1]; ss.az = out[stage - 1][2];
+                r = run_pair(ctx, ss, sc, 0, n, MODE_ACC, pl, 0, 0.0, s);
+                if (r != NB_OK) return r;
+            }
+            K.stage = 4;
+            {
+                Timed t(ctx, s, 1, 0);
+                const hipError_t e = launch_rk4(K, fp32, s);
+                if (e != hipSuccess) return hipfail(ctx, e, "RK4 update launch");
+            }
+            r = run_pair(ctx, st, sc, 0, n, fmode, fpl, 0, 0.0, s);
+            if (r != NB_OK) return r;
+        }
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_step_rk4");
+    }
 }
 
 nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm, nbody_diag_t *out_dev,

@@ -74,6 +74,9 @@ def _load():
         "nbody_step_kdk": ([P, S, PR, D, I64, V]),
         "nbody_step_o4": ([P, S, PR, D, I64, V]),
         "nbody_diag": ([P, S, PR, V, V]),
+        "nbody_accel_jerk": ([P, S, V, V, V, PR, V]),
+        "nbody_step_hermite": ([P, S, V, V, V, PR, D, I64, V]),
+        "nbody_step_rk4": ([P, S, PR, D, I64, V]),
         "nbody_surface_density": ([P, S, I32, I32, D, D, D, D, V, V]),
         "nbody_batch_create": ([P, I32, ctypes.POINTER(I64), PR, ctypes.POINTER(D), ctypes.c_uint32,
                                 ctypes.POINTER(P)]),
@@ -149,7 +152,20 @@ class System:
         for k in ("x", "y", "z", "vx", "vy", "vz", "m", "ax", "ay", "az"):
             if k in d:
                 s.t[k].copy_(torch.as_tensor(d[k], dtype=torch.float64))
+        if "jx" in d:
+            for k in ("jx", "jy", "jz"):
+                s.jerk(k).copy_(torch.as_tensor(d[k], dtype=torch.float64))
         return s
+
+    def jerk(self, k: str) -> torch.Tensor:
+        """The jerk array k (jx, jy or jz) of the Hermite scheme, allocated
+        on first use."""
+        if self.t.get(k) is None:
+            self.t[k] = torch.zeros(self.n, dtype=torch.float64, device=self.t["x"].device)
+        return self.t[k]
+
+    def jerk_ptrs(self):
+        return [ctypes.c_void_p(self.jerk(k).data_ptr() if self.n > 0 else None) for k in ("jx", "jy", "jz")]
 
     def __getitem__(self, k):
         return self.t[k]
@@ -201,6 +217,24 @@ def nbody_step_o4(ctx, sys: System, prm: Params, dt: float, nsteps: int, stream=
     cs, cp = sys.c(), prm.c()
     _check(ctx, _lib.nbody_step_o4(ctx, ctypes.byref(cs), ctypes.byref(cp), float(dt), int(nsteps),
                                    _stream(stream)))
+
+
+def nbody_accel_jerk(ctx, sys: System, prm: Params, stream=None):
+    """a and the jerk (into sys['jx'], ['jy'], ['jz']) at the current state."""
+    cs, cp = sys.c(), prm.c()
+    _check(ctx, _lib.nbody_accel_jerk(ctx, ctypes.byref(cs), *sys.jerk_ptrs(), ctypes.byref(cp), _stream(stream)))
+
+
+def nbody_step_hermite(ctx, sys: System, prm: Params, dt: float, nsteps: int, stream=None):
+    cs, cp = sys.c(), prm.c()
+    _check(ctx, _lib.nbody_step_hermite(ctx, ctypes.byref(cs), *sys.jerk_ptrs(), ctypes.byref(cp), float(dt),
+                                        int(nsteps), _stream(stream)))
+
+
+def nbody_step_rk4(ctx, sys: System, prm: Params, dt: float, nsteps: int, stream=None):
+    cs, cp = sys.c(), prm.c()
+    _check(ctx, _lib.nbody_step_rk4(ctx, ctypes.byref(cs), ctypes.byref(cp), float(dt), int(nsteps),
+                                    _stream(stream)))
 
 
 def nbody_diag(ctx, sys: System, prm: Params, out: torch.Tensor | None = None, stream=None):

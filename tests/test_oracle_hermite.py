@@ -152,3 +152,14 @@ def test_free_particle_exact(orc):
         s = orc.State(ic, eps=0.1)
         getattr(s, "step_" + scheme)(0.125, 64)
         assert s["x"][0] == 5.0 and s["y"][0] == 0.0 and s["vz"][0] == 0.125
+
+
+def test_scales_bound_the_sums(orc):
+    # the magnitude sums bound the sums themselves (triangle inequality) and
+    # the acceleration scale equals the accel oracle's
+    p = wl.plummer(400, 24)
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(p, 1.0, 0.01, want_scale=True)
+    assert np.all(np.sqrt(ax ** 2 + ay ** 2 + az ** 2) <= A * (1 + 1e-12))
+    assert np.all(np.sqrt(jx ** 2 + jy ** 2 + jz ** 2) <= J * (1 + 1e-12))
+    A2 = orc.accel(p["x"], p["y"], p["z"], p["m"], 1.0, 0.01, want_scale=True)[3]
+    assert np.max(np.abs(A - A2) / A2) < 1e-13
