@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 METRIC = "pair-interactions/s at N=2^20 (FP64 vs mixed @ stated err); p50/p99 latency"
 FLOPS_PER_INTERACTION = 20  # conventional count for the softened pair term
+JERK_FLOPS_PER_INTERACTION = 42  # the 20 above + relative velocity (3), r.u (5), factor (2), jerk FMAs (12)
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "fp32": 157.3}  # MI355X vector peaks
 DTYPE = {"fp64": "f64", "mixed": "f32 pair / f64 accumulate+state", "fp32": "f32"}
 KERNEL_SOURCES = ["paper_1803_01190_amd/csrc/accel.hip", "paper_1803_01190_amd/csrc/nbody_internal.h"]
@@ -85,11 +86,12 @@ def main():
     ap.add_argument("--retune", action="store_true", help="autotune even if a cached plan exists")
     ap.add_argument("--plans-out", default=None, help="write the plans used in plan-cache form")
     ap.add_argument("--workload", default="disk",
-                    choices=["disk", "batched", "serving", "integrators", "longrun"],
+                    choices=["disk", "batched", "serving", "integrators", "longrun", "hermite"],
                     help="disk: the headline N=2^20 step (default); batched: 256 independent systems "
                          "in one persistent launch vs one launch per system; serving: Poisson "
                          "request stream through the continuous-batching loop; longrun: 10^4-step "
-                         "self-gravitating disk in each precision (conservation and density maps)")
+                         "self-gravitating disk in each precision (conservation and density maps); "
+                         "hermite: the fourth-order Hermite step at N=2^20")
     ap.add_argument("--long-n", type=int, default=1 << 17, help="longrun: particles")
     ap.add_argument("--long-steps", type=int, default=10000, help="longrun: steps per run")
     ap.add_argument("--long-runs", default="fp64,fp64_alt,mixed,fp32",
@@ -122,6 +124,8 @@ def main():
         return bench_integrators(args)
     if args.workload == "longrun":
         return bench_longrun(args)
+    if args.workload == "hermite":
+        return bench_hermite(args)
     dev = torch.device("cuda:0")
     n, dt, eps = args.n, 1e-3, 0.02
     halo = wl.default_halo()
@@ -505,6 +509,106 @@ def bench_longrun(args):
                                   f"KDK dt={dt:.6g} (outer period / 4000), seed {seed}", "n": n},
            "table2": out, "maps": maps}
     print(json.dumps(res))
+    ctx.close()
+
+
+def bench_hermite(args):
+    """The fourth-order Hermite step at N = 2^20 on the headline disk (eps =
+    0.02, halo): one acceleration-and-jerk pair pass per step with the
+    corrector fused, timed per precision like the KDK step; errors of a and j
+    against the oracle on sampled rows."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1803_01190_amd import nbody as nb
+
+    dev = torch.device("cuda:0")
+    n, dt, eps = args.n, 1e-3, 0.02
+    halo = wl.default_halo()
+    ic = wl.exp_disk(n, 2)
+    precs = [p.strip() for p in args.precs.split(",") if p.strip()]
+    ctx = nb.Context(0)
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(n, size=min(args.sample_rows, n), replace=False))
+    rows_t = torch.as_tensor(rows, device=dev)
+    results = {}
+    for prec in precs:
+        prm = nb.Params(G=1.0, eps=eps, prec=nb.PREC[prec], halo=True, halo_v2=halo.v2, halo_rc=halo.rc)
+        s = nb.System.from_arrays(ic, device=dev)
+        nb.nbody_accel_jerk(ctx.h, s, prm)
+        aj0 = torch.stack([s[k][rows_t] for k in ("ax", "ay", "az", "jx", "jy", "jz")]).cpu().numpy()
+        for _ in range(args.warmup):
+            nb.nbody_step_hermite(ctx.h, s, prm, dt, 1)
+        d0 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
+        torch.cuda.synchronize()
+        nb.nbody_profile_read(ctx.h)
+        nb.nbody_profile_enable(ctx.h, True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        evs[0].record()
+        for k in range(args.steps):
+            nb.nbody_step_hermite(ctx.h, s, prm, dt, 1)
+            evs[k + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        nb.nbody_profile_enable(ctx.h, False)
+        prof = nb.nbody_profile_read(ctx.h)
+        d1 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
+        step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+        inter = float(n) * float(n)
+        pair_ms = prof["accel_ms"] / max(prof["accel_launches"], 1)
+        tflops = JERK_FLOPS_PER_INTERACTION * inter / (pair_ms * 1e-3) / 1e12
+        results[prec] = {
+            "value": args.steps * inter / wall, "ms_per_step": 1e3 * wall / args.steps,
+            "latency_ms": {"p50": percentile(step_ms, 0.5), "p99": percentile(step_ms, 0.99)},
+            "pair_kernel_ms": pair_ms, "pair_launches": prof["accel_launches"],
+            "update_ms_per_step": prof["update_ms"] / max(args.steps, 1), "achieved_tflops": tflops,
+            "drift": {"dE_rel": abs(d1["E"] - d0["E"]) / abs(d0["E"]),
+                      "dLz_rel": abs(d1["Lz"] - d0["Lz"]) / abs(d0["Lz"]), "steps": args.steps},
+            "_aj0": aj0,
+        }
+        log(f"[hermite] {prec}: {results[prec]['value']:.4e} pair-int/s, {1e3 * wall / args.steps:.1f} ms/step, "
+            f"pair kernel {pair_ms:.1f} ms ({tflops:.1f} TFLOP/s at {JERK_FLOPS_PER_INTERACTION} flop/pair)")
+        del s
+        torch.cuda.empty_cache()
+    cpu, errs = None, {}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        cores = oracle.max_threads()
+        t0 = time.perf_counter()
+        ref = oracle.accel_jerk(ic, 1.0, eps, oracle.Halo(halo.v2, halo.rc), want_scale=True, rows=rows)
+        el = time.perf_counter() - t0
+        cpu = {"value": rows.size * float(n) / el, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+               "sample": f"{rows.size} seeded rows of the N=2^20 disk, acceleration and jerk over all {n} "
+                         f"sources (float64, {el:.1f} s on {cores} threads)"}
+        A, J = ref[6], ref[7]
+        for prec, r in results.items():
+            g = r["_aj0"]
+            da = np.sqrt(((g[:3] - np.stack(ref[:3])) ** 2).sum(0))
+            dj = np.sqrt(((g[3:] - np.stack(ref[3:6])) ** 2).sum(0))
+            errs[prec] = {"a_cond": float(np.max(da / A)), "j_cond": float(np.max(dj / J))}
+        log(f"[hermite] cpu oracle {cpu['value']:.3e} pair-int/s; errors {errs}")
+    head = precs[0]
+    r0 = results[head]
+    out = {
+        "metric": "pair-interactions/s at N=2^20, fourth-order Hermite step (acceleration and jerk per pair)",
+        "value": r0["value"], "unit": "pair-interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r0["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[head], "data": "synthetic",
+        "config": {"workload": f"exponential stellar disk N={n} + fixed isothermal halo, eps={eps}, "
+                               f"Hermite dt={dt}", "n": n, "integrator": "hermite", "precision": head},
+        "latency_ms": r0["latency_ms"],
+        "roofline": {"bound": "alu", "achieved": r0["achieved_tflops"], "peak": PEAK_TFLOPS[head],
+                     "unit": "TFLOP/s", "frac": r0["achieved_tflops"] / PEAK_TFLOPS[head], "traffic": None,
+                     "kernel": "acceleration and jerk (k_pair_jerk)",
+                     "flops_per_interaction": JERK_FLOPS_PER_INTERACTION, "interactions_per_launch": inter},
+        "cpu_baseline": cpu, "errors": errs or None,
+        "per_precision": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
+    }
+    print(json.dumps(out))
     ctx.close()
 
 

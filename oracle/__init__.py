@@ -81,8 +81,8 @@ def _load(path: str | None = None):
         lib.orc_step_o4.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp,
                                     _dbl, _i64, _dbl, _dbl, _int, _int]
         lib.orc_diag.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _D, _int]
-        lib.orc_accel_jerk.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _D, _D, _D, _D,
-                                       _D, _D, _D, _D, _int]
+        lib.orc_accel_jerk.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _I, _i64, _D, _D,
+                                       _D, _D, _D, _D, _D, _D, _int]
         lib.orc_step_hermite.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl,
                                          _dbl, hp, _dbl, _i64, _int]
         lib.orc_step_rk4.argtypes = [_i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _dbl, _dbl, hp, _dbl,
@@ -240,17 +240,21 @@ def diag(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0) -> dict:
     return dict(zip(DIAG_KEYS, out.tolist()))
 
 
-def accel_jerk(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0, want_scale=False):
+def accel_jerk(s: dict, G=1.0, eps=0.0, halo: Halo | None = None, nthreads=0, want_scale=False, rows=None):
     """Acceleration (Eqs. (1)-(2)) and its time derivative along the motion,
-    plus the halo's when given.  Returns (ax, ay, az, jx, jy, jz), and with
-    want_scale also the sums of the self-gravity terms' magnitudes (A, J)."""
+    plus the halo's when given, for all particles or for ``rows``.  Returns
+    (ax, ay, az, jx, jy, jz), and with want_scale also the sums of the
+    self-gravity terms' magnitudes (A, J)."""
     lib = _load()
     a = {k: _f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
     n = a["x"].size
-    out = [np.zeros(n) for _ in range(8 if want_scale else 6)]
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = n if r is None else r.size
+    out = [np.zeros(cnt) for _ in range(8 if want_scale else 6)]
     hp, _keep = _halo(halo)
     sc = [_p(o) for o in out[6:]] if want_scale else [None, None]
-    lib.orc_accel_jerk(n, *[_p(a[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], G, eps, hp,
+    rp = None if r is None else r.ctypes.data_as(_I)
+    lib.orc_accel_jerk(n, *[_p(a[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], G, eps, hp, rp, cnt,
                        *[_p(o) for o in out[:6]], *sc, nthreads)
     return tuple(out)
 

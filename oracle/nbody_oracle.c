@@ -298,16 +298,19 @@ static void jerk_one(int64_t n, const double *x, const double *y, const double *
     o[0] = ax; o[1] = ay; o[2] = az; o[3] = jx; o[4] = jy; o[5] = jz; o[6] = sa; o[7] = sj;
 }
 
-/* acceleration and jerk of every particle (plus the halo's when h->on);
- * sa, sj (nullable): the sums of the self-gravity terms' magnitudes, scales
- * for conditioned error measures. */
+/* acceleration and jerk (plus the halo's when h->on) of every particle, or of
+ * the nrows targets listed in rows (outputs of length nrows); sa, sj
+ * (nullable): the sums of the self-gravity terms' magnitudes, scales for
+ * conditioned error measures. */
 void orc_accel_jerk(int64_t n, const double *x, const double *y, const double *z, const double *vx,
                     const double *vy, const double *vz, const double *m, double G, double eps,
-                    const orc_halo *h, double *ax, double *ay, double *az, double *jx, double *jy,
-                    double *jz, double *sa, double *sj, int nthreads) {
+                    const orc_halo *h, const int64_t *rows, int64_t nrows, double *ax, double *ay,
+                    double *az, double *jx, double *jy, double *jz, double *sa, double *sj, int nthreads) {
     set_threads(nthreads);
+    const int64_t cnt = rows ? nrows : n;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t q = 0; q < cnt; ++q) {
+        const int64_t i = rows ? rows[q] : q;
         double o[8];
         jerk_one(n, x, y, z, vx, vy, vz, m, G, eps, i, o);
         if (h && h->on) {
@@ -322,9 +325,9 @@ void orc_accel_jerk(int64_t n, const double *x, const double *y, const double *z
             o[4] -= g * vy[i] + hh * rv * y[i];
             o[5] -= g * vz[i] + hh * rv * z[i];
         }
-        ax[i] = o[0]; ay[i] = o[1]; az[i] = o[2]; jx[i] = o[3]; jy[i] = o[4]; jz[i] = o[5];
-        if (sa) sa[i] = o[6];
-        if (sj) sj[i] = o[7];
+        ax[q] = o[0]; ay[q] = o[1]; az[q] = o[2]; jx[q] = o[3]; jy[q] = o[4]; jz[q] = o[5];
+        if (sa) sa[q] = o[6];
+        if (sj) sj[q] = o[7];
     }
 }
 
@@ -353,8 +356,8 @@ void orc_step_hermite(int64_t n, double *x, double *y, double *z, double *vx, do
             pvy[i] = vy[i] + ay[i] * dt + jy[i] * dt * dt / 2.0;
             pvz[i] = vz[i] + az[i] * dt + jz[i] * dt * dt / 2.0;
         }
-        orc_accel_jerk(n, px, py, pz, pvx, pvy, pvz, m, G, eps, h, bx, by, bz, kx, ky, kz, NULL, NULL,
-                       nthreads);
+        orc_accel_jerk(n, px, py, pz, pvx, pvy, pvz, m, G, eps, h, NULL, 0, bx, by, bz, kx, ky, kz, NULL,
+                       NULL, nthreads);
         ++g_force_evals;
         for (int64_t i = 0; i < n; ++i) {
             const double wx = vx[i] + (ax[i] + bx[i]) * dt / 2.0 + (jx[i] - kx[i]) * dt * dt / 12.0;

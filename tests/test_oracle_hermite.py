@@ -163,3 +163,13 @@ def test_scales_bound_the_sums(orc):
     assert np.all(np.sqrt(jx ** 2 + jy ** 2 + jz ** 2) <= J * (1 + 1e-12))
     A2 = orc.accel(p["x"], p["y"], p["z"], p["m"], 1.0, 0.01, want_scale=True)[3]
     assert np.max(np.abs(A - A2) / A2) < 1e-13
+
+
+def test_rows_subset_equals_full(orc):
+    p = wl.plummer(500, 25)
+    halo = orc.Halo(1.0, 1.0)
+    full = orc.accel_jerk(p, 1.0, 0.01, halo, want_scale=True)
+    rows = np.array([0, 7, 499, 250, 3])
+    sub = orc.accel_jerk(p, 1.0, 0.01, halo, want_scale=True, rows=rows)
+    for f, g in zip(full, sub):
+        assert np.array_equal(f[rows], g)
