@@ -145,6 +145,9 @@ def main():
     if not args.retune:
         table = nb.read_plans(args.plans_in) if args.plans_in else nb.read_plans()
         pinned = {k: v[str(log2n)] for k, v in table.items() if str(log2n) in v}
+        for k, v in pinned.items():  # potential-pass and jerk plans of this size
+            if "/" in k:
+                nb.nbody_plan_set(ctx.h, nb.plan_code(k), n, v)
     results = {}
     for prec in precs:
         p = nb.PREC[prec]
@@ -529,6 +532,7 @@ def bench_hermite(args):
     ic = wl.exp_disk(n, 2)
     precs = [p.strip() for p in args.precs.split(",") if p.strip()]
     ctx = nb.Context(0)
+    nb.load_plans(ctx.h)
     rng = np.random.default_rng(7)
     rows = np.sort(rng.choice(n, size=min(args.sample_rows, n), replace=False))
     rows_t = torch.as_tensor(rows, device=dev)

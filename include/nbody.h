@@ -286,6 +286,18 @@ NBODY_API nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, co
 
 /* ---- launch plans and autotuning --------------------------------------- */
 
+/* Kernel class of a launch plan, or-ed into the precision argument of
+ * nbody_plan_get, nbody_plan_set and nbody_autotune (bits 8-15):
+ *   NB_PLAN_ACCEL      the acceleration sum (nbody_accel, the steps, batches);
+ *   NB_PLAN_POTENTIAL  the float64 potential pass of nbody_diag (256 lanes,
+ *                      R = 1 or 2, jsrc 0 or 1);
+ *   NB_PLAN_JERK       the acceleration-and-jerk sum of the Hermite scheme
+ *                      (256 lanes, R = 1 or 2, jsrc 0).
+ * Plans of each class are pinned per precision and size class separately. */
+#define NB_PLAN_ACCEL 0x000
+#define NB_PLAN_POTENTIAL 0x100
+#define NB_PLAN_JERK 0x200
+
 /* Plan the single-system pair sum uses for (prec, n).  Plans are keyed by
  * (prec, ceil(log2 n)); an untuned key gets a fixed heuristic plan. */
 NBODY_API nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, nbody_plan *out);

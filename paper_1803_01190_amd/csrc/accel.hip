@@ -483,8 +483,10 @@ hipError_t go_pair(const PairLaunch &P, hipStream_t s) {
 template <int PREC, int MODE, int JSRC>
 hipError_t pick_rb(const PairLaunch &P, hipStream_t s) {
     if constexpr (MODE != MODE_ACC) {
-        // potential variants: one fixed shape
-        if (P.R == 1 && P.block == 256) return go_pair<PREC, 1, 256, MODE, JSRC>(P, s);
+        // potential variants: 256 lanes, one or two targets per lane
+        if (P.block != 256) return hipErrorInvalidValue;
+        if (P.R == 1) return go_pair<PREC, 1, 256, MODE, JSRC>(P, s);
+        if (P.R == 2) return go_pair<PREC, 2, 256, MODE, JSRC>(P, s);
         return hipErrorInvalidValue;
     } else {
         switch (P.block * 8 + P.R) {
@@ -579,7 +581,7 @@ int pair_batched_occupancy(int prec, int R, int block, int mode) {
 
 bool pair_config_supported(int prec, int R, int block, int jsrc, int mode) {
     if (prec < 0 || prec > 2 || (jsrc != 0 && jsrc != 1)) return false;
-    if (mode != MODE_ACC) return R == 1 && block == 256;
+    if (mode != MODE_ACC) return block == 256 && (R == 1 || R == 2);
     return (block == 128 || block == 256) && (R == 1 || R == 2 || R == 4);
 }
 

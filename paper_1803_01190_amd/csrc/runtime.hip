@@ -297,9 +297,20 @@ nbody_status kdk_single(nbody_ctx *ctx, const State &st, const SysConst &sc, con
     return run_pair(ctx, st, sc, 0, sc.n, mode, pl, 1, h, s);
 }
 
+// Potential pass of the diagnostics (mode 2): a pinned plan of class
+// NB_PLAN_POTENTIAL, else R = 1, 256 lanes, LDS tiles, split to fill the chip.
+// The fused acceleration-and-potential variant (mode 1) always takes the
+// heuristic shape.
 nbody_plan mode_plan(nbody_ctx *ctx, int prec, int64_t n, int mode) {
     if (mode == MODE_ACC) return plan_for(ctx, prec, n);
-    // the potential variants exist for one shape only: R = 1, 256 lanes, LDS
+    if (mode == MODE_PHI) {
+        auto it = ctx->plans.find({prec | NB_PLAN_POTENTIAL, ilog2_ceil(n)});
+        if (it != ctx->plans.end()) {
+            nbody_plan p = it->second;
+            if (prec == P_FP32) p.split = 1;
+            return p;
+        }
+    }
     nbody_plan pl{1, 256, 1, 0};
     if (prec == P_FP32) return pl;  // one float32 running sum, as in plan_for
     const int64_t nblk = (n + 255) / 256;
@@ -379,23 +390,37 @@ nbody_status batch_steps(nbody_ctx *ctx, nbody_batch *b, const nbody_sys *all, i
     return NB_OK;
 }
 
-// Launch plan of the acceleration-and-jerk sum: 256 lanes, LDS tiles, two
-// targets per lane when there are enough workgroups, sources split until the
-// chip has two workgroups per CU (never for float32, as for the acceleration).
+// Launch plan of the acceleration-and-jerk sum: a pinned plan of class
+// NB_PLAN_JERK, else 256 lanes, LDS tiles, R and the source split below
+// (never a split for float32, as for the acceleration).
 nbody_plan jerk_plan(const nbody_ctx *ctx, int prec, int64_t n) {
+    auto it = ctx->plans.find({prec | NB_PLAN_JERK, ilog2_ceil(n)});
+    if (it != ctx->plans.end()) {
+        nbody_plan p = it->second;
+        if (prec == P_FP32) p.split = 1;
+        return p;
+    }
+    // measured on gfx950: two targets per lane from N = 2^17 on, and up to
+    // eight workgroups per CU (the kernel holds about 120 VGPRs)
     nbody_plan p{2, 256, 1, 0};
-    const int64_t want = 2LL * ctx->cus;
-    if ((n + 511) / 512 < want) p.R = 1;
+    if (n < (1 << 17)) p.R = 1;
     if (prec == P_FP32) return p;
+    const int64_t want = 8LL * ctx->cus;
     const int64_t nblk = (n + 256LL * p.R - 1) / (256LL * p.R);
     while (nblk * p.split < want && n / (2LL * p.split) >= 512 && p.split < 64) p.split *= 2;
     return p;
 }
 
-nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, hipStream_t s) {
+bool jerk_plan_supported(int prec, const nbody_plan &p) {
+    return p.block == 256 && (p.R == 1 || p.R == 2) && p.jsrc == 0 && (prec != P_FP32 || p.split == 1);
+}
+
+nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, const nbody_plan &pl, hipStream_t s) {
     const int64_t rows = J.i1 - J.i0;
     if (rows <= 0) return NB_OK;
-    const nbody_plan pl = jerk_plan(ctx, J.sc.prec, J.sc.n);
+    if (!jerk_plan_supported(J.sc.prec, pl))
+        return fail(ctx, NB_ENOTSUP, "unsupported jerk plan R=%d block=%d split=%d jsrc=%d", pl.R, pl.block,
+                    pl.split, pl.jsrc);
     J.R = pl.R;
     J.block = pl.block;
     J.split = pl.split;
@@ -561,7 +586,7 @@ nbody_status nbody_accel_jerk(nbody_ctx *ctx, const nbody_sys *sys, double *jx, 
         J.sc = make_sysconst(prm, 0, sys->n, 0.0);
         J.i0 = 0;
         J.i1 = sys->n;
-        return run_jerk(ctx, J, (hipStream_t)stream);
+        return run_jerk(ctx, J, jerk_plan(ctx, prm->prec, sys->n), (hipStream_t)stream);
     } catch (...) {
         return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_jerk");
     }
@@ -602,13 +627,14 @@ nbody_status nbody_step_hermite(nbody_ctx *ctx, nbody_sys *sys, double *jx, doub
         J.corr = 1;
         J.dt = dt;
         const int fp32 = prm->prec == NB_FP32;
+        const nbody_plan pl = jerk_plan(ctx, prm->prec, n);
         for (int64_t k = 0; k < nsteps; ++k) {
             {
                 Timed t(ctx, s, 1, 0);
                 const hipError_t e = launch_hermite_predict(H, fp32, s);
                 if (e != hipSuccess) return hipfail(ctx, e, "Hermite predictor launch");
             }
-            r = run_jerk(ctx, J, s);
+            r = run_jerk(ctx, J, pl, s);
             if (r != NB_OK) return r;
         }
         return NB_OK;
@@ -943,67 +969,118 @@ nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys 
 
 // ---- plans -------------------------------------------------------------------
 
-nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, nbody_plan *out) {
+// The plan argument's precision carries the kernel class in bits 8-15.
+static nbody_status split_class(nbody_ctx *ctx, int32_t code, int *prec, int *cls) {
+    *prec = code & 0xff;
+    *cls = code & ~0xff;
+    if (*prec < 0 || *prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", *prec);
+    if (*cls != NB_PLAN_ACCEL && *cls != NB_PLAN_POTENTIAL && *cls != NB_PLAN_JERK)
+        return fail(ctx, NB_EINVAL, "unknown plan class 0x%x", *cls);
+    return NB_OK;
+}
+
+static nbody_plan effective_plan(nbody_ctx *ctx, int prec, int cls, int64_t n) {
+    if (cls == NB_PLAN_POTENTIAL) return mode_plan(ctx, prec, n, MODE_PHI);
+    if (cls == NB_PLAN_JERK) return jerk_plan(ctx, prec, n);
+    return plan_for(ctx, prec, n);
+}
+
+static bool class_plan_supported(int prec, int cls, const nbody_plan &p) {
+    if (p.split < 1 || p.split > 1024) return false;
+    if (cls == NB_PLAN_JERK) return p.block == 256 && (p.R == 1 || p.R == 2) && p.jsrc == 0;
+    return pair_config_supported(prec, p.R, p.block, p.jsrc, cls == NB_PLAN_POTENTIAL ? MODE_PHI : MODE_ACC);
+}
+
+nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec_class, int64_t n, nbody_plan *out) {
     if (!ctx) return NB_EINVAL;
     if (!out) return fail(ctx, NB_EINVAL, "out is NULL");
-    if (prec < 0 || prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", prec);
+    int prec = 0, cls = 0;
+    nbody_status r = split_class(ctx, prec_class, &prec, &cls);
+    if (r != NB_OK) return r;
     if (n < 0) return fail(ctx, NB_EINVAL, "n must be >= 0");
-    *out = plan_for(ctx, prec, n);
+    *out = effective_plan(ctx, prec, cls, n);
     return NB_OK;
 }
 
-nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, const nbody_plan *p) {
+nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec_class, int64_t n, const nbody_plan *p) {
     if (!ctx) return NB_EINVAL;
-    if (prec < 0 || prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", prec);
+    int prec = 0, cls = 0;
+    nbody_status r = split_class(ctx, prec_class, &prec, &cls);
+    if (r != NB_OK) return r;
     if (n < 0) return fail(ctx, NB_EINVAL, "n must be >= 0");
     if (!p) {
-        ctx->plans.erase({prec, ilog2_ceil(n)});
+        ctx->plans.erase({prec | cls, ilog2_ceil(n)});
         return NB_OK;
     }
-    if (p->split < 1 || p->split > 1024 || !pair_config_supported(prec, p->R, p->block, p->jsrc, MODE_ACC))
+    if (!class_plan_supported(prec, cls, *p))
         return fail(ctx, NB_EINVAL, "unsupported plan R=%d block=%d split=%d jsrc=%d", p->R, p->block, p->split, p->jsrc);
-    ctx->plans[{prec, ilog2_ceil(n)}] = *p;
+    ctx->plans[{prec | cls, ilog2_ceil(n)}] = *p;
     return NB_OK;
 }
 
-nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms, nbody_plan *out) {
+nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec_class, int64_t n, double budget_ms, nbody_plan *out) {
     if (!ctx) return NB_EINVAL;
-    if (prec < 0 || prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", prec);
+    int prec = 0, cls = 0;
+    nbody_status r0 = split_class(ctx, prec_class, &prec, &cls);
+    if (r0 != NB_OK) return r0;
     if (n < 1 || n > INT32_MAX) return fail(ctx, NB_EINVAL, "n must be in [1, 2^31)");
     if (!is_finite(budget_ms)) return fail(ctx, NB_EINVAL, "budget_ms must be finite");
     try {
         DevGuard g(ctx->device);
-        // synthetic particles: a uniform cube, equal masses, in one scratch block
+        // synthetic particles: a uniform cube, equal masses, small random
+        // velocities, in one scratch block:
+        // x y z m | ax ay az | vx vy vz | phi | jx jy jz
+        const size_t nn = (size_t)n;
         double *buf = nullptr;
-        HIPCHECK(ctx, hipMalloc((void **)&buf, sizeof(double) * 7 * (size_t)n));
-        std::vector<double> h(7 * (size_t)n);
+        HIPCHECK(ctx, hipMalloc((void **)&buf, sizeof(double) * 14 * nn));
+        std::vector<double> h(14 * nn, 0.0);
         uint64_t s = 0x9E3779B97F4A7C15ULL;
-        for (size_t i = 0; i < 3 * (size_t)n; ++i) {
+        auto uni = [&]() {
             s = s * 6364136223846793005ULL + 1442695040888963407ULL;
-            h[i] = (double)(s >> 11) * (1.0 / 9007199254740992.0) - 0.5;
-        }
-        for (int64_t i = 0; i < n; ++i) h[3 * n + i] = 1.0 / (double)n;
-        hipError_t e = hipMemcpy(buf, h.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice);
+            return (double)(s >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        };
+        for (size_t i = 0; i < 3 * nn; ++i) h[i] = uni();
+        for (size_t i = 0; i < nn; ++i) h[3 * nn + i] = 1.0 / (double)n;
+        for (size_t i = 7 * nn; i < 10 * nn; ++i) h[i] = 0.1 * uni();
+        hipError_t e = hipMemcpy(buf, h.data(), sizeof(double) * 14 * nn, hipMemcpyHostToDevice);
         if (e != hipSuccess) { (void)hipFree(buf); return hipfail(ctx, e, "autotune upload"); }
         State st{};
         st.x = buf; st.y = buf + n; st.z = buf + 2 * n; st.m = buf + 3 * n;
         st.ax = buf + 4 * n; st.ay = buf + 5 * n; st.az = buf + 6 * n;
+        st.vx = buf + 7 * n; st.vy = buf + 8 * n; st.vz = buf + 9 * n;
+        double *phi = buf + 10 * n;
         nbody_params p{1.0, 0.01, prec, 0, 0.0, 0.0};
         SysConst sc = make_sysconst(&p, 0, n, 0.0);
         // long source sweeps behave alike, so large systems are timed
         // against a prefix of the sources with the full target grid
         const int64_t nsrc = std::min<int64_t>(n, 32768);
         sc.n = nsrc;
+        JerkLaunch J{};
+        J.x = st.x; J.y = st.y; J.z = st.z; J.vx = st.vx; J.vy = st.vy; J.vz = st.vz; J.m = st.m;
+        J.ax = st.ax; J.ay = st.ay; J.az = st.az;
+        J.jx = buf + 11 * n; J.jy = buf + 12 * n; J.jz = buf + 13 * n;
+        J.sc = sc;
+        J.i0 = 0;
+        J.i1 = n;
+        State sp = st;
+        sp.phi = phi;
+        auto launch = [&](const nbody_plan &pl) -> nbody_status {
+            if (cls == NB_PLAN_JERK) return run_jerk(ctx, J, pl, nullptr);
+            if (cls == NB_PLAN_POTENTIAL) return run_pair(ctx, sp, sc, 0, n, MODE_PHI, pl, 0, 0.0, nullptr);
+            return run_pair(ctx, st, sc, 0, n, MODE_ACC, pl, 0, 0.0, nullptr);
+        };
         std::vector<nbody_plan> cand;
-        const nbody_plan base = heuristic_plan(ctx, prec, n);
+        const nbody_plan base = effective_plan(ctx, prec, cls, n);
         cand.push_back(base);
-        for (int jsrc = 0; jsrc <= 1; ++jsrc)
+        const int max_split = prec == P_FP32 ? 1 : 64;
+        for (int jsrc = 0; jsrc <= (cls == NB_PLAN_JERK ? 0 : 1); ++jsrc)
             for (int block : {256, 128})
                 for (int R : {1, 2, 4})
-                    for (int split = 1; split <= (prec == P_FP32 ? 1 : 64); split *= 2) {
+                    for (int split = 1; split <= max_split; split *= 2) {
+                        nbody_plan c{R, block, split, jsrc};
+                        if (!class_plan_supported(prec, cls, c)) continue;
                         const int64_t nblk = (n + (int64_t)block * R - 1) / ((int64_t)block * R);
                         if (split > 1 && (nblk * split > 16LL * ctx->cus || n / split < 2LL * block)) continue;
-                        nbody_plan c{R, block, split, jsrc};
                         if (c.R == base.R && c.block == base.block && c.split == base.split && c.jsrc == base.jsrc) continue;
                         cand.push_back(c);
                     }
@@ -1018,15 +1095,12 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budg
         for (size_t c = 0; c < cand.size(); ++c) {
             if (c > 0 && budget_ms > 0 && spent >= budget_ms) break;
             const nbody_plan &pl = cand[c];
-            // sources are [0, nsrc): scale the split for the true n
-            nbody_plan run = pl;
             float ms = 0.0f;
-            result = run_pair(ctx, st, sc, 0, n, MODE_ACC, run, 0, 0.0, nullptr);  // warm-up
+            result = launch(pl);  // warm-up
             if (result != NB_OK) break;
             (void)hipEventRecord(a, nullptr);
             const int reps = 2;
-            for (int k = 0; k < reps && result == NB_OK; ++k)
-                result = run_pair(ctx, st, sc, 0, n, MODE_ACC, run, 0, 0.0, nullptr);
+            for (int k = 0; k < reps && result == NB_OK; ++k) result = launch(pl);
             (void)hipEventRecord(bev, nullptr);
             if (result != NB_OK) break;
             e = hipEventSynchronize(bev);
@@ -1042,7 +1116,7 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budg
         (void)hipDeviceSynchronize();
         (void)hipFree(buf);
         if (result != NB_OK) return result;
-        ctx->plans[{prec, ilog2_ceil(n)}] = best;
+        ctx->plans[{prec | cls, ilog2_ceil(n)}] = best;
         if (out) *out = best;
         return NB_OK;
     } catch (...) {

@@ -23,6 +23,8 @@ NB_OK, NB_EINVAL, NB_ENOMEM, NB_EHIP, NB_ENOTSUP = 0, -1, -2, -3, -4
 NB_FP64, NB_MIXED, NB_FP32 = 0, 1, 2
 NB_BATCH_GRAPH = 1
 PREC = {"fp64": NB_FP64, "mixed": NB_MIXED, "fp32": NB_FP32}
+NB_PLAN_ACCEL, NB_PLAN_POTENTIAL, NB_PLAN_JERK = 0x000, 0x100, 0x200
+PLAN_CLASS = {"accel": NB_PLAN_ACCEL, "potential": NB_PLAN_POTENTIAL, "jerk": NB_PLAN_JERK}
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "ax", "ay", "az")
 
 
@@ -327,8 +329,16 @@ def nbody_plan_set(ctx, prec: int, n: int, plan: dict | None):
 TUNED_PLANS = os.path.join(_HERE, "tuned_plans.json")
 
 
+def plan_code(key: str) -> int:
+    """Precision-and-class code of a plan-cache key: "fp64" (the acceleration
+    sum) or "fp64/potential", "mixed/jerk", ..."""
+    prec, _, cls = key.partition("/")
+    return PREC[prec] | PLAN_CLASS[cls or "accel"]
+
+
 def read_plans(path: str = TUNED_PLANS, arch: str = "gfx950") -> dict:
-    """{prec_name: {log2n: plan}} from a plan-cache file (empty if absent)."""
+    """{key: {log2n: plan}} from a plan-cache file (empty if absent); keys as
+    in plan_code."""
     import json
     try:
         with open(path) as f:
@@ -340,9 +350,9 @@ def read_plans(path: str = TUNED_PLANS, arch: str = "gfx950") -> dict:
 def load_plans(ctx, path: str = TUNED_PLANS, arch: str = "gfx950") -> int:
     """Pin every plan of a plan-cache file; returns how many were pinned."""
     k = 0
-    for prec, table in read_plans(path, arch).items():
+    for key, table in read_plans(path, arch).items():
         for log2n, plan in table.items():
-            nbody_plan_set(ctx, PREC[prec], 1 << int(log2n), plan)
+            nbody_plan_set(ctx, plan_code(key), 1 << int(log2n), plan)
             k += 1
     return k
 

@@ -95,3 +95,14 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "4"],
                        capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_plan_class_constants_match_header():
+    import re
+    from paper_1803_01190_amd import nbody as nb
+    text = open(HEADER).read()
+    consts = {m.group(1): int(m.group(2), 16) for m in re.finditer(r"#define (NB_PLAN_\w+) (0x[0-9a-fA-F]+)", text)}
+    assert consts == {"NB_PLAN_ACCEL": nb.NB_PLAN_ACCEL, "NB_PLAN_POTENTIAL": nb.NB_PLAN_POTENTIAL,
+                      "NB_PLAN_JERK": nb.NB_PLAN_JERK}
+    assert nb.plan_code("fp64/potential") == nb.NB_FP64 | nb.NB_PLAN_POTENTIAL
+    assert nb.plan_code("mixed") == nb.NB_MIXED

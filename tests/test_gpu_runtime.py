@@ -95,3 +95,44 @@ def test_autotune_returns_a_valid_plan(nb, ctx, orc):
     nb.nbody_plan_set(ctx, nb.NB_FP32, n, {"R": 2, "block": 128, "split": 8, "jsrc": 0})
     assert nb.nbody_plan_get(ctx, nb.NB_FP32, n)["split"] == 1
     nb.nbody_plan_set(ctx, nb.NB_FP32, n, None)
+
+
+def test_plan_classes(nb, ctx, orc):
+    # potential-pass and jerk plans are pinned separately from the
+    # acceleration plan and change nothing beyond rounding
+    n = 3000
+    ic = wl.plummer(n, 35)
+    prm = nb.Params(eps=0.01)
+    pot = nb.NB_FP64 | nb.NB_PLAN_POTENTIAL
+    jerk = nb.NB_FP64 | nb.NB_PLAN_JERK
+    accel_plan = nb.nbody_plan_get(ctx, nb.NB_FP64, n)
+    ref = orc.diag(ic, eps=0.01)
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(ic, 1.0, 0.01, want_scale=True)
+    for pp in ({"R": 2, "block": 256, "split": 2, "jsrc": 1}, {"R": 1, "block": 256, "split": 1, "jsrc": 0}):
+        nb.nbody_plan_set(ctx, pot, n, pp)
+        assert nb.nbody_plan_get(ctx, pot, n) == pp
+        assert nb.nbody_plan_get(ctx, nb.NB_FP64, n) == accel_plan
+        s = nb.System.from_arrays(ic)
+        d = nb.diag_dict(nb.nbody_diag(ctx, s, prm))
+        assert abs(d["W"] - ref["W"]) <= 1e-12 * abs(ref["W"]), pp
+    for jp in ({"R": 1, "block": 256, "split": 4, "jsrc": 0}, {"R": 2, "block": 256, "split": 1, "jsrc": 0}):
+        nb.nbody_plan_set(ctx, jerk, n, jp)
+        assert nb.nbody_plan_get(ctx, jerk, n) == jp
+        s = nb.System.from_arrays(ic)
+        nb.nbody_accel_jerk(ctx, s, prm)
+        torch.cuda.synchronize()
+        g = s.numpy()
+        dj = np.sqrt((g["jx"] - jx) ** 2 + (g["jy"] - jy) ** 2 + (g["jz"] - jz) ** 2)
+        assert np.max(dj / J) <= 1e-12, jp
+    for bad_code, bad in ((jerk, {"R": 2, "block": 256, "split": 1, "jsrc": 1}),
+                          (jerk, {"R": 4, "block": 256, "split": 1, "jsrc": 0}),
+                          (pot, {"R": 2, "block": 128, "split": 1, "jsrc": 0}),
+                          (nb.NB_FP64 | 0x300, {"R": 1, "block": 256, "split": 1, "jsrc": 0})):
+        with pytest.raises(nb.NBodyError) as ei:
+            nb.nbody_plan_set(ctx, bad_code, n, bad)
+        assert ei.value.status == nb.NB_EINVAL
+    for code in (pot, jerk):
+        tuned = nb.nbody_autotune(ctx, code, n, 100.0)
+        assert tuned["block"] == 256 and tuned["R"] in (1, 2)
+        assert nb.nbody_plan_get(ctx, code, n) == tuned
+        nb.nbody_plan_set(ctx, code, n, None)
