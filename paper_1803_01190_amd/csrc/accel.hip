@@ -31,6 +31,12 @@
 namespace nb {
 namespace {
 
+// Smallest normal numbers: with a softening whose square is not normal the
+// kernels take a variant that drops pairs whose r^2 is below these (the self
+// pair and coincident particles), whose terms would overflow.
+constexpr double kMinNormal64 = 2.2250738585072014e-308;
+constexpr float kMinNormal32 = 1.17549435e-38f;
+
 struct alignas(16) JD { double x, y, z, m; };            // float64 source
 struct alignas(16) JM { double x, y, z; float m, pad; }; // mixed source
 struct alignas(16) JF { float x, y, z, m; };             // float32 source
@@ -63,7 +69,6 @@ struct Lane {
     using F = typename Tr<PREC>::A;          // inner (per-tile) sum type
     using O = typename std::conditional<PREC == P_FP32, float, double>::type;  // outer sum type
     Ti xi[R], yi[R], zi[R];
-    int32_t li[R];                           // target index local to the system
     // Correction coefficients held in registers: gfx9 VOP3 instructions take
     // no literal operands, so without this the compiler rematerialises them
     // with v_mov instructions in every pair.
@@ -80,10 +85,14 @@ struct Lane {
 // the source mass is left out of the pair term and applied once to the run's
 // sum (float64: fold(); mixed: the per-tile flush), saving one multiply per
 // pair.
-template <int PREC, int R, int MODE, bool SAFE, bool UM = false>
+// MASK (potential modes, only for the few source groups that can hold one of
+// the workgroup's own targets): bit r of selfbits marks the source as target
+// slot r itself, whose term is left out.  Elsewhere no pair is the self pair,
+// and in the acceleration the self pair adds nothing (zero separation).
+template <int PREC, int R, int MODE, bool SAFE, bool UM = false, bool MASK = false>
 __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy, double sz,
                                          double sm, float fx, float fy, float fz, float fm,
-                                         int32_t lj, double eps2, float eps2f) {
+                                         double eps2, float eps2f, uint32_t selfbits = 0) {
     static_assert(!UM || (MODE == MODE_ACC && PREC != P_FP32), "equal-mass runs: fp64/mixed accelerations");
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -91,8 +100,8 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
             const double dx = sx - L.xi[r], dy = sy - L.yi[r], dz = sz - L.zi[r];
             const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
             double y = __builtin_amdgcn_rsq(r2);
-            if constexpr (SAFE) y = (r2 > 0.0) ? y : 0.0;
-            if constexpr (MODE == MODE_PHI || MODE == MODE_ACC_PHI) y = (lj == L.li[r]) ? 0.0 : y;
+            if constexpr (SAFE) y = (r2 >= kMinNormal64) ? y : 0.0;
+            if constexpr (MASK) y = ((selfbits >> r) & 1u) ? 0.0 : y;
             const double y2 = y * y;
             const double e = __builtin_fma(r2, y2, -1.0);
             if constexpr (MODE != MODE_PHI) {
@@ -122,8 +131,8 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
             }
             const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
             float y = __builtin_amdgcn_rsqf(r2);
-            if constexpr (SAFE) y = (r2 > 0.0f) ? y : 0.0f;
-            if constexpr (MODE == MODE_PHI || MODE == MODE_ACC_PHI) y = (lj == L.li[r]) ? 0.0f : y;
+            if constexpr (SAFE) y = (r2 >= kMinNormal32) ? y : 0.0f;
+            if constexpr (MASK) y = ((selfbits >> r) & 1u) ? 0.0f : y;
             const float my = UM ? y : fm * y;
             if constexpr (MODE != MODE_PHI) {
                 const float s = my * (y * y);
@@ -182,7 +191,7 @@ __device__ __forceinline__ T in_vgpr(T v) {
 
 template <int PREC, int R>
 __device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int64_t ib,
-                                          int64_t ilim, int64_t sys_off, int BLOCK) {
+                                          int64_t ilim, int BLOCK) {
     const int t = threadIdx.x;
     if constexpr (PREC == P_FP64) {
         L.km15 = in_vgpr(-1.5);
@@ -195,7 +204,6 @@ __device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int
         L.xi[r] = ok ? (typename Tr<PREC>::Ti)st.x[i] : 0;
         L.yi[r] = ok ? (typename Tr<PREC>::Ti)st.y[i] : 0;
         L.zi[r] = ok ? (typename Tr<PREC>::Ti)st.z[i] : 0;
-        L.li[r] = (int32_t)(i - sys_off);
         L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0;
         L.ox[r] = L.oy[r] = L.oz[r] = L.op[r] = 0;
         L.ux[r] = L.uy[r] = L.uz[r] = 0.0;
@@ -203,13 +211,28 @@ __device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int
     L.mrun = 0.0;
 }
 
-// Sum sources [jb, je) (global indices; the system starts at sys_off) into L.
+// Sum sources [jb, je) (global indices) into L.
 // LDS-staged source tiles of BLOCK particles.  A tile whose sources all have
 // the same mass (decided by a block-wide vote, so the branch is uniform)
 // takes the equal-mass pair term.
+// Source interaction with the general (not equal-mass) pair term.
+template <int PREC, int R, int MODE, bool SAFE, bool MASK = false>
+__device__ __forceinline__ void interact_src(Lane<PREC, R> &L, const typename Tr<PREC>::J &e, double eps2,
+                                             float eps2f, uint32_t selfbits = 0) {
+    if constexpr (PREC == P_FP32)
+        interact<PREC, R, MODE, SAFE, false, MASK>(L, 0, 0, 0, 0, e.x, e.y, e.z, e.m, eps2, eps2f, selfbits);
+    else if constexpr (PREC == P_MIXED)
+        interact<PREC, R, MODE, SAFE, false, MASK>(L, e.x, e.y, e.z, 0, 0, 0, 0, e.m, eps2, eps2f, selfbits);
+    else
+        interact<PREC, R, MODE, SAFE, false, MASK>(L, e.x, e.y, e.z, e.m, 0, 0, 0, 0, eps2, eps2f, selfbits);
+}
+
+// The workgroup's targets are [ib, ib + R BLOCK) (slot r of lane t is
+// ib + r BLOCK + t); potential modes mask the self pair in the tiles that
+// overlap them.
 template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
 __device__ __forceinline__ void sweep_lds(Lane<PREC, R> &L, const State &st, int64_t jb,
-                                          int64_t je, int64_t sys_off, double eps2, float eps2f,
+                                          int64_t je, int64_t ib, double eps2, float eps2f,
                                           typename Tr<PREC>::J *tile) {
     constexpr bool kUM = MODE == MODE_ACC && PREC != P_FP32;
     const int t = threadIdx.x;
@@ -218,7 +241,27 @@ __device__ __forceinline__ void sweep_lds(Lane<PREC, R> &L, const State &st, int
         const typename Tr<PREC>::J mine = load_src<PREC>(st, j, j < je);
         tile[t] = mine;
         __syncthreads();
-        const int32_t lj0 = (int32_t)(jt - sys_off);
+        if constexpr (MODE != MODE_ACC) {
+            if (jt < ib + (int64_t)R * BLOCK && ib < jt + BLOCK) {
+                // position in this tile of each slot's own source (-1: not here)
+                int32_t kr[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t d = ib + (int64_t)r * BLOCK + t - jt;
+                    kr[r] = (d >= 0 && d < BLOCK) ? (int32_t)d : -1;
+                }
+#pragma unroll 2
+                for (int k = 0; k < BLOCK; ++k) {
+                    uint32_t bits = 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) bits |= (kr[r] == k) ? (1u << r) : 0u;
+                    interact_src<PREC, R, MODE, SAFE, true>(L, tile[k], eps2, eps2f, bits);
+                }
+                flush(L);
+                __syncthreads();
+                continue;
+            }
+        }
         bool um = false;
         double m0 = 0.0;
         if constexpr (kUM) {
@@ -233,20 +276,12 @@ __device__ __forceinline__ void sweep_lds(Lane<PREC, R> &L, const State &st, int
 #pragma unroll 4
                 for (int k = 0; k < BLOCK; ++k) {
                     const typename Tr<PREC>::J e = tile[k];
-                    interact<PREC, R, MODE, SAFE, true>(L, e.x, e.y, e.z, 0, 0, 0, 0, 0, lj0 + k, eps2, eps2f);
+                    interact<PREC, R, MODE, SAFE, true>(L, e.x, e.y, e.z, 0, 0, 0, 0, 0, eps2, eps2f);
                 }
             }
         } else {
 #pragma unroll 4
-            for (int k = 0; k < BLOCK; ++k) {
-                const typename Tr<PREC>::J e = tile[k];
-                if constexpr (PREC == P_FP32)
-                    interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, e.x, e.y, e.z, e.m, lj0 + k, eps2, eps2f);
-                else if constexpr (PREC == P_MIXED)
-                    interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, 0, 0, 0, 0, e.m, lj0 + k, eps2, eps2f);
-                else
-                    interact<PREC, R, MODE, SAFE>(L, e.x, e.y, e.z, e.m, 0, 0, 0, 0, lj0 + k, eps2, eps2f);
-            }
+            for (int k = 0; k < BLOCK; ++k) interact_src<PREC, R, MODE, SAFE>(L, tile[k], eps2, eps2f);
         }
         flush(L, um, m0);
         __syncthreads();
@@ -265,6 +300,30 @@ __device__ __forceinline__ bool range_equal_mass(const double *m, int64_t jb, in
     return __syncthreads_and(ok) != 0;
 }
 
+// Bit r set if source j is this lane's target slot r (ib + r BLOCK + lane).
+template <int R, int BLOCK>
+__device__ __forceinline__ uint32_t self_bits(int64_t ib, int64_t j) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) bits |= (ib + (int64_t)r * BLOCK + threadIdx.x == j) ? (1u << r) : 0u;
+    return bits;
+}
+
+// One source given as float64 values (scalar path).
+template <int PREC, int R, int MODE, bool SAFE, bool UM, bool MASK>
+__device__ __forceinline__ void scalar_src(Lane<PREC, R> &L, double sx, double sy, double sz, double sm,
+                                           double eps2, float eps2f, uint32_t bits) {
+    if constexpr (UM)
+        interact<PREC, R, MODE, SAFE, true, MASK>(L, sx, sy, sz, 0, 0, 0, 0, 0, eps2, eps2f, bits);
+    else if constexpr (PREC == P_FP32)
+        interact<PREC, R, MODE, SAFE, false, MASK>(L, 0, 0, 0, 0, (float)sx, (float)sy, (float)sz, (float)sm, eps2,
+                                                   eps2f, bits);
+    else if constexpr (PREC == P_MIXED)
+        interact<PREC, R, MODE, SAFE, false, MASK>(L, sx, sy, sz, 0, 0, 0, 0, (float)sm, eps2, eps2f, bits);
+    else
+        interact<PREC, R, MODE, SAFE, false, MASK>(L, sx, sy, sz, sm, 0, 0, 0, 0, eps2, eps2f, bits);
+}
+
 // Same sum with sources read as wave-uniform values (scalar loads into
 // SGPRs).  Groups of U sources; the tail is summed one source at a time so
 // nothing past je is read.  UM: every source of the range has mass L.mrun
@@ -272,7 +331,7 @@ __device__ __forceinline__ bool range_equal_mass(const double *m, int64_t jb, in
 // once at the end.
 template <int PREC, int R, int BLOCK, int MODE, bool SAFE, bool UM>
 __device__ __forceinline__ void sweep_scalar(Lane<PREC, R> &L, const State &st, int64_t jb,
-                                             int64_t je, int64_t sys_off, double eps2,
+                                             int64_t je, int64_t ib, double eps2,
                                              float eps2f) {
     using CD = const __attribute__((address_space(4))) double;
     CD *X = (CD *)st.x;
@@ -289,31 +348,27 @@ __device__ __forceinline__ void sweep_scalar(Lane<PREC, R> &L, const State &st, 
             sx[u] = X[j + u]; sy[u] = Y[j + u]; sz[u] = Z[j + u];
             sm[u] = UM ? 0.0 : M[j + u];
         }
+        // potential modes: groups that overlap the workgroup's own targets
+        // mask the self pair (a uniform branch)
+        const bool own = MODE != MODE_ACC && j < ib + (int64_t)R * BLOCK && ib < j + U;
+        if (own) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t lj = (int32_t)(j + u - sys_off);
-            if constexpr (UM)
-                interact<PREC, R, MODE, SAFE, true>(L, sx[u], sy[u], sz[u], 0, 0, 0, 0, 0, lj, eps2, eps2f);
-            else if constexpr (PREC == P_FP32)
-                interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, (float)sx[u], (float)sy[u], (float)sz[u], (float)sm[u], lj, eps2, eps2f);
-            else if constexpr (PREC == P_MIXED)
-                interact<PREC, R, MODE, SAFE>(L, sx[u], sy[u], sz[u], 0, 0, 0, 0, (float)sm[u], lj, eps2, eps2f);
-            else
-                interact<PREC, R, MODE, SAFE>(L, sx[u], sy[u], sz[u], sm[u], 0, 0, 0, 0, lj, eps2, eps2f);
+            for (int u = 0; u < U; ++u)
+                scalar_src<PREC, R, MODE, SAFE, UM, true>(L, sx[u], sy[u], sz[u], sm[u], eps2, eps2f,
+                                                          self_bits<R, BLOCK>(ib, j + u));
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                scalar_src<PREC, R, MODE, SAFE, UM, false>(L, sx[u], sy[u], sz[u], sm[u], eps2, eps2f, 0u);
         }
         if (j + U >= flush_at) { flush(L, UM, L.mrun); flush_at += BLOCK; }
     }
     for (; j < je; ++j) {
         const double sx = X[j], sy = Y[j], sz = Z[j], sm = UM ? 0.0 : M[j];
-        const int32_t lj = (int32_t)(j - sys_off);
-        if constexpr (UM)
-            interact<PREC, R, MODE, SAFE, true>(L, sx, sy, sz, 0, 0, 0, 0, 0, lj, eps2, eps2f);
-        else if constexpr (PREC == P_FP32)
-            interact<PREC, R, MODE, SAFE>(L, 0, 0, 0, 0, (float)sx, (float)sy, (float)sz, (float)sm, lj, eps2, eps2f);
-        else if constexpr (PREC == P_MIXED)
-            interact<PREC, R, MODE, SAFE>(L, sx, sy, sz, 0, 0, 0, 0, (float)sm, lj, eps2, eps2f);
+        if constexpr (MODE != MODE_ACC)
+            scalar_src<PREC, R, MODE, SAFE, UM, true>(L, sx, sy, sz, sm, eps2, eps2f, self_bits<R, BLOCK>(ib, j));
         else
-            interact<PREC, R, MODE, SAFE>(L, sx, sy, sz, sm, 0, 0, 0, 0, lj, eps2, eps2f);
+            scalar_src<PREC, R, MODE, SAFE, UM, false>(L, sx, sy, sz, sm, eps2, eps2f, 0u);
     }
     flush(L, UM, L.mrun);
     fold(L);
@@ -321,16 +376,16 @@ __device__ __forceinline__ void sweep_scalar(Lane<PREC, R> &L, const State &st, 
 
 template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
 __device__ __forceinline__ void sweep_scalar_any(Lane<PREC, R> &L, const State &st, int64_t jb,
-                                                 int64_t je, int64_t sys_off, double eps2,
+                                                 int64_t je, int64_t ib, double eps2,
                                                  float eps2f) {
     if constexpr (MODE == MODE_ACC && PREC != P_FP32) {
         if (range_equal_mass<BLOCK>(st.m, jb, je)) {
             L.mrun = st.m[jb];
-            sweep_scalar<PREC, R, BLOCK, MODE, SAFE, true>(L, st, jb, je, sys_off, eps2, eps2f);
+            sweep_scalar<PREC, R, BLOCK, MODE, SAFE, true>(L, st, jb, je, ib, eps2, eps2f);
             return;
         }
     }
-    sweep_scalar<PREC, R, BLOCK, MODE, SAFE, false>(L, st, jb, je, sys_off, eps2, eps2f);
+    sweep_scalar<PREC, R, BLOCK, MODE, SAFE, false>(L, st, jb, je, ib, eps2, eps2f);
 }
 
 // Raw sums of lane slot r (outer for MIXED, inner otherwise).
@@ -385,11 +440,11 @@ __global__ __launch_bounds__(BLOCK) void k_pair(PairLaunch P, int64_t chunk) {
     const int64_t jb = (int64_t)blockIdx.y * chunk;
     const int64_t je = (jb + chunk < P.sc.n) ? jb + chunk : P.sc.n;
     Lane<PREC, R> L;
-    lane_init<PREC, R>(L, P.st, ib, P.i1, 0, BLOCK);
+    lane_init<PREC, R>(L, P.st, ib, P.i1, BLOCK);
     if constexpr (JSRC == 0)
-        sweep_lds<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f, tile);
+        sweep_lds<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, ib, P.sc.eps2, P.sc.eps2f, tile);
     else
-        sweep_scalar_any<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, 0, P.sc.eps2, P.sc.eps2f);
+        sweep_scalar_any<PREC, R, BLOCK, MODE, SAFE>(L, P.st, jb, je, ib, P.sc.eps2, P.sc.eps2f);
     const int64_t rows = P.i1 - P.i0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -443,12 +498,12 @@ __global__ __launch_bounds__(BLOCK) void k_pair_batched(BatchLaunch B) {
         const SysConst sc = B.sys[it.sys];
         const int64_t ilim = sc.off + sc.n;
         Lane<PREC, R> L;
-        lane_init<PREC, R>(L, B.st, it.i0, ilim, sc.off, BLOCK);
+        lane_init<PREC, R>(L, B.st, it.i0, ilim, BLOCK);
         const bool safe = (PREC == P_FP64) ? sc.safe64 : sc.safe32;
         if (safe)
-            sweep_lds<PREC, R, BLOCK, MODE, true>(L, B.st, sc.off, ilim, sc.off, sc.eps2, sc.eps2f, tile);
+            sweep_lds<PREC, R, BLOCK, MODE, true>(L, B.st, sc.off, ilim, it.i0, sc.eps2, sc.eps2f, tile);
         else
-            sweep_lds<PREC, R, BLOCK, MODE, false>(L, B.st, sc.off, ilim, sc.off, sc.eps2, sc.eps2f, tile);
+            sweep_lds<PREC, R, BLOCK, MODE, false>(L, B.st, sc.off, ilim, it.i0, sc.eps2, sc.eps2f, tile);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t i = it.i0 + (int64_t)r * BLOCK + threadIdx.x;

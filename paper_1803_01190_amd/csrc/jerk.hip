@@ -70,7 +70,7 @@ __device__ __forceinline__ void interact(JLane<PREC, R> &L, const typename JT<PR
             const double du = s.u - L.u[r], dv = s.v - L.v[r], dw = s.w - L.w[r];
             const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
             double y = __builtin_amdgcn_rsq(r2);
-            if constexpr (SAFE) y = (r2 > 0.0) ? y : 0.0;
+            if constexpr (SAFE) y = (r2 >= 2.2250738585072014e-308) ? y : 0.0;  // drop non-normal r^2
             const double y2 = y * y;
             const double e = __builtin_fma(r2, y2, -1.0);
             const double c3 = __builtin_fma(L.km15, e, 1.0);
@@ -97,7 +97,7 @@ __device__ __forceinline__ void interact(JLane<PREC, R> &L, const typename JT<PR
             }
             const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
             float y = __builtin_amdgcn_rsqf(r2);
-            if constexpr (SAFE) y = (r2 > 0.0f) ? y : 0.0f;
+            if constexpr (SAFE) y = (r2 >= 1.17549435e-38f) ? y : 0.0f;
             const float y2 = y * y;
             const float sm = (m * y) * y2;
             const float rv = __builtin_fmaf(dx, du, __builtin_fmaf(dy, dv, dz * dw));

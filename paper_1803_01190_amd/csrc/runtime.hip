@@ -298,9 +298,10 @@ nbody_status kdk_single(nbody_ctx *ctx, const State &st, const SysConst &sc, con
 }
 
 // Potential pass of the diagnostics (mode 2): a pinned plan of class
-// NB_PLAN_POTENTIAL, else R = 1, 256 lanes, LDS tiles, split to fill the chip.
-// The fused acceleration-and-potential variant (mode 1) always takes the
-// heuristic shape.
+// NB_PLAN_POTENTIAL, else 256 lanes, LDS tiles, two targets per lane from
+// N = 2^17 on and a source split up to eight workgroups per CU (measured on
+// gfx950).  The fused acceleration-and-potential variant (mode 1) always
+// takes this heuristic shape.
 nbody_plan mode_plan(nbody_ctx *ctx, int prec, int64_t n, int mode) {
     if (mode == MODE_ACC) return plan_for(ctx, prec, n);
     if (mode == MODE_PHI) {
@@ -311,10 +312,10 @@ nbody_plan mode_plan(nbody_ctx *ctx, int prec, int64_t n, int mode) {
             return p;
         }
     }
-    nbody_plan pl{1, 256, 1, 0};
+    nbody_plan pl{n >= (1 << 17) ? 2 : 1, 256, 1, 0};
     if (prec == P_FP32) return pl;  // one float32 running sum, as in plan_for
-    const int64_t nblk = (n + 255) / 256;
-    while (nblk * pl.split < 2LL * ctx->cus && n / (2LL * pl.split) >= 512 && pl.split < 64) pl.split *= 2;
+    const int64_t nblk = (n + 256LL * pl.R - 1) / (256LL * pl.R);
+    while (nblk * pl.split < 8LL * ctx->cus && n / (2LL * pl.split) >= 512 && pl.split < 64) pl.split *= 2;
     return pl;
 }
 

@@ -111,6 +111,22 @@ def test_potential(nb, ctx, orc, prec):
     assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec]
 
 
+@pytest.mark.parametrize("prec,eps", [("fp64", 1e-160), ("mixed", 1e-25), ("fp32", 1e-25), ("fp64", 1e-150)])
+def test_tiny_softening(nb, ctx, orc, prec, eps):
+    # a softening whose square is not a normal number in the compute
+    # precision (or, for 1e-150, is) leaves the self pair out of the
+    # acceleration and the potential; distinct particles are far apart
+    print(f"[case] tiny eps {prec} {eps}", flush=True)
+    ic = wl.plummer(700, 12)
+    ref, phi_ref, A = oracle_accel(orc, ic, eps)
+    got = run_accel(nb, ctx, ic, eps, nb.PREC[prec], phi=True)
+    assert all(np.all(np.isfinite(got[k])) for k in ("ax", "ay", "az", "phi"))
+    e = errs(got, ref, A)
+    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec], e
+    rel = np.max(np.abs(got["phi"] - phi_ref) / np.abs(phi_ref))
+    assert rel <= {"fp64": 1e-13, "mixed": 2e-5, "fp32": 1e-3}[prec], rel
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_zero_softening_coincident(nb, ctx, orc, prec):
     # eps = 0 with coincident particles: their mutual term is defined as zero

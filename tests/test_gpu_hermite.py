@@ -75,6 +75,16 @@ def test_coincident_pair_without_softening(nb, ctx, orc):
     assert cond_err(a, (ax, ay, az), A) <= 1e-12 and cond_err(j, (jx, jy, jz), J) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,eps", [("fp64", 1e-160), ("mixed", 1e-25)])
+def test_tiny_softening_jerk(nb, ctx, orc, prec, eps):
+    # a softening whose square is not normal: the self pair drops out
+    ic = wl.plummer(700, 209)
+    a, j = gpu_aj(nb, ctx, ic, nb.Params(eps=eps, prec=nb.PREC[prec]))
+    assert np.all(np.isfinite(np.concatenate([*a, *j])))
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(ic, 1.0, eps, want_scale=True)
+    assert cond_err(a, (ax, ay, az), A) <= TOL[prec] and cond_err(j, (jx, jy, jz), J) <= TOL[prec]
+
+
 def run_steps(nb, ctx, ic, prm, scheme, dt, steps):
     s = nb.System.from_arrays(ic)
     if scheme == "hermite":
