@@ -288,7 +288,8 @@ NBODY_API nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, co
 
 /* Kernel class of a launch plan, or-ed into the precision argument of
  * nbody_plan_get, nbody_plan_set and nbody_autotune (bits 8-15):
- *   NB_PLAN_ACCEL      the acceleration sum (nbody_accel, the steps, batches);
+ *   NB_PLAN_ACCEL      the acceleration sum (nbody_accel and the single-system steps;
+ *                      a batch uses its own plan, see nbody_batch_get_plan);
  *   NB_PLAN_POTENTIAL  the float64 potential pass of nbody_diag (256 lanes,
  *                      R = 1 or 2, jsrc 0 or 1);
  *   NB_PLAN_JERK       the acceleration-and-jerk sum of the Hermite scheme

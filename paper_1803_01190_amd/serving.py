@@ -219,7 +219,7 @@ class GpuBackend(Backend):
     graph replay is off by default here: the set of active requests changes
     every few steps, and each change would need a new capture."""
 
-    BATCH_PLAN = {"R": 1, "block": 256, "split": 1, "jsrc": 0}
+    BATCH_PLAN = {"R": 2, "block": 256, "split": 1, "jsrc": 0}
 
     def __init__(self, ctx, device="cuda", graph: bool = False, keep_state: bool = True,
                  diagnostics: bool = True):
@@ -262,7 +262,7 @@ class GpuBackend(Backend):
         with self.torch.cuda.stream(self.stream):
             s = nb.System.from_arrays(ic, device=self.device)
         prm = self._params(req)
-        # a(t0) under the plan every batch uses (R 1, 256 lanes, no split,
+        # a(t0) under the plan every batch uses (R 2, 256 lanes, no split,
         # LDS), which gives the same bits as the batched kernel; this avoids
         # creating (and synchronously destroying) a one-system batch
         nb.nbody_plan_set(self.ctx, prm.prec, req.n, self.BATCH_PLAN)
