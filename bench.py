@@ -86,17 +86,19 @@ def main():
     ap.add_argument("--retune", action="store_true", help="autotune even if a cached plan exists")
     ap.add_argument("--plans-out", default=None, help="write the plans used in plan-cache form")
     ap.add_argument("--workload", default="disk",
-                    choices=["disk", "batched", "serving", "integrators", "longrun", "hermite"],
+                    choices=["disk", "batched", "serving", "integrators", "longrun", "hermite", "scaling"],
                     help="disk: the headline N=2^20 step (default); batched: 256 independent systems "
                          "in one persistent launch vs one launch per system; serving: Poisson "
                          "request stream through the continuous-batching loop; longrun: 10^4-step "
                          "self-gravitating disk in each precision (conservation and density maps); "
-                         "hermite: the fourth-order Hermite step at N=2^20")
+                         "hermite: the fourth-order Hermite step at N=2^20; scaling: one step for "
+                         "N = 2^17..2^23 (Table 1)")
     ap.add_argument("--long-n", type=int, default=1 << 17, help="longrun: particles")
     ap.add_argument("--long-steps", type=int, default=10000, help="longrun: steps per run")
     ap.add_argument("--long-runs", default="fp64,fp64_alt,mixed,fp32",
                     help="longrun: runs (fp64_alt: float64 with another summation order)")
     ap.add_argument("--out-dir", default="gpurun_out/longrun", help="longrun: series and maps")
+    ap.add_argument("--scaling-max-log2", type=int, default=23, help="scaling: largest N = 2^k")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
     ap.add_argument("--graph", action="store_true", help="serving: replay steps from HIP graphs")
     ap.add_argument("--profile-run", action="store_true",
@@ -126,6 +128,8 @@ def main():
         return bench_longrun(args)
     if args.workload == "hermite":
         return bench_hermite(args)
+    if args.workload == "scaling":
+        return bench_scaling(args)
     dev = torch.device("cuda:0")
     n, dt, eps = args.n, 1e-3, 0.02
     halo = wl.default_halo()
@@ -613,6 +617,69 @@ def bench_hermite(args):
         "per_precision": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
     }
     print(json.dumps(out))
+    ctx.close()
+
+
+# The paper's Table 1: one KDK step on one Tesla K80 GPU, seconds, for
+# N = 128K ... 8192K particles (N x 1024), single and double precision.
+PAPER_TABLE1_K80 = {
+    "n_k": [128, 256, 512, 1024, 2048, 4096, 8192],
+    "sp_s": [0.4, 1.7, 6.9, 27.4, 109.6, 438.0, 1754.0],
+    "dp_s": [0.9, 3.7, 15.0, 60.0, 240.0, 960.0, 3840.0],
+}
+
+
+def bench_scaling(args):
+    """One KDK step of the disk (eps = 0.02, halo) for N = 2^17 ... 2^max on
+    one GPU, per precision: the single-GPU columns of the paper's Table 1
+    (whose disk model differs; its K80 times are listed as context).  Sizes
+    without a tuned plan are autotuned first (bounded budget)."""
+    import torch
+
+    import workloads as wl
+    from paper_1803_01190_amd import nbody as nb
+
+    precs = [p.strip() for p in args.precs.split(",") if p.strip()]
+    ctx = nb.Context(0)
+    nb.load_plans(ctx.h)
+    halo = wl.default_halo()
+    table = nb.read_plans()
+    rows = []
+    for log2n in range(17, args.scaling_max_log2 + 1):
+        n = 1 << log2n
+        ic = wl.exp_disk(n, 2)
+        for prec in precs:
+            p = nb.PREC[prec]
+            if str(log2n) not in table.get(prec, {}):
+                nb.nbody_autotune(ctx.h, p, n, 1500.0)
+            plan = nb.nbody_plan_get(ctx.h, p, n)
+            prm = nb.Params(eps=0.02, prec=p, halo=True, halo_v2=halo.v2, halo_rc=halo.rc)
+            s = nb.System.from_arrays(ic)
+            nb.nbody_accel(ctx.h, s, prm)  # a(t0); also warms up the same kernel and plan
+            steps = max(1, min(args.steps, int(2e12 // (float(n) * n)) + 1))
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nb.nbody_step_kdk(ctx.h, s, prm, 1e-3, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / steps
+            rows.append({"n": n, "prec": prec, "step_s": t, "pair_interactions_per_s": float(n) * n / t,
+                         "plan": plan, "steps": steps})
+            log(f"[scaling] N=2^{log2n} {prec}: {t:.4f} s/step, {float(n) * n / t:.3e} pair-int/s, plan {plan}")
+            del s
+            torch.cuda.empty_cache()
+    head = "mixed" if "mixed" in precs else precs[0]
+    top = [r for r in rows if r["prec"] == head][-1]
+    res = {"metric": "one KDK step time vs N on one GPU (the paper's Table 1, single-GPU columns)",
+           "value": top["pair_interactions_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,
+           "steps": top["steps"], "warmup": 0, "ms_per_step": 1e3 * top["step_s"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[head], "data": "synthetic",
+           "config": {"workload": f"exponential stellar disk N=2^17..2^{args.scaling_max_log2} + fixed isothermal "
+                                  "halo, eps=0.02, KDK dt=1e-3", "precisions": precs},
+           "rows": rows, "paper_table1_k80_one_gpu": PAPER_TABLE1_K80}
+    print(json.dumps(res))
     ctx.close()
 
 
