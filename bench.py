@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--long-runs", default="fp64,fp64_alt,mixed,fp32",
                     help="longrun: runs (fp64_alt: float64 with another summation order)")
     ap.add_argument("--out-dir", default="gpurun_out/longrun", help="longrun: series and maps")
+    ap.add_argument("--stop-at", type=int, default=None,
+                    help="longrun: stop each run at this step and save it for --resume-dir")
+    ap.add_argument("--resume-dir", default=None, help="longrun: continue the runs saved there")
     ap.add_argument("--scaling-max-log2", type=int, default=23, help="scaling: largest N = 2^k")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
     ap.add_argument("--graph", action="store_true", help="serving: replay steps from HIP graphs")
@@ -458,6 +461,7 @@ def bench_longrun(args):
     import numpy as np
 
     import workloads as wl
+    from paper_1803_01190_amd import checkpoint
     from paper_1803_01190_amd import longrun as lr
     from paper_1803_01190_amd import nbody as nb
 
@@ -485,15 +489,29 @@ def bench_longrun(args):
                 log(f"[longrun] {name} step {done}/{steps} ({time.perf_counter() - t0:.0f}s) "
                     f"dE {dv['dE_rel'][-1]:.2e} dL {dv['dL_rel'][-1]:.2e} dP {dv['dP_abs'][-1]:.2e}")
 
-        rec = lr.run(ctx.h, ic, prm, dt, steps, every=50, maps_at=maps_at, grid=grid, plan=plan,
-                     progress=progress)
+        # a run may be cut into pieces (--stop-at, then --resume-dir with the saved piece)
+        run_ic, resume = ic, None
+        if args.resume_dir:
+            rstem = os.path.join(args.resume_dir, f"resume_{name}_{n}")
+            st, _, _, step, _ = checkpoint.load(rstem + "_state.npz")
+            run_ic = st.numpy()
+            del st
+            resume = (lr.Record.load(rstem), step)
+            log(f"[longrun] {name}: resuming at step {step}")
+        rec = lr.run(ctx.h, run_ic, prm, dt, steps, every=50, maps_at=maps_at, grid=grid, plan=plan,
+                     progress=progress, resume=resume, stop_at=args.stop_at)
+        if rec.done < steps:
+            stem = os.path.join(args.out_dir, f"resume_{name}_{n}")
+            checkpoint.save(stem + "_state.npz", nb.System.from_arrays(rec.final), prm, step=rec.done)
+            rec.save(stem)
+            log(f"[longrun] {name}: stopped at step {rec.done}, saved {stem}*")
         recs[name] = rec
-        out[name] = {**rec.table2(), "wall_s": rec.busy_s, "evals": rec.evals,
+        out[name] = {**rec.table2(), "wall_s": rec.busy_s, "evals": rec.evals, "done": rec.done,
                      "pair_interactions_per_s": lr.interactions_per_s(n, rec)}
         log(f"[longrun] {name}: {out[name]}")
     ref = recs.get("fp64")
     maps = {}
-    if ref is not None:
+    if ref is not None and all(rec.done == steps for rec in recs.values()):
         for name, rec in recs.items():
             if name == "fp64":
                 continue
@@ -505,7 +523,8 @@ def bench_longrun(args):
         json.dump({"n": n, "dt": dt, "steps": steps, "eps": eps, "period": period, "table2": out,
                    "maps": maps, "series": series}, f)
     np.savez_compressed(os.path.join(args.out_dir, f"maps_{n}.npz"),
-                        **{f"{name}_{k}": rec.maps[k] for name, rec in recs.items() for k in maps_at})
+                        **{f"{name}_{k}": rec.maps[k] for name, rec in recs.items() for k in maps_at
+                           if k in rec.maps})
     head = "mixed" if "mixed" in out else next(iter(out))
     res = {"metric": "10^4-step conservation (Table 2 quantities) and density-map deviation vs float64",
            "value": out[head]["pair_interactions_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,

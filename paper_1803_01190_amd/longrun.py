@@ -45,6 +45,7 @@ class Record:
     busy_s: float = 0.0                        # wall time of the step calls only
     evals: int = 0
     final: dict | None = None                  # host copy of the last state
+    done: int = 0                              # steps taken so far
 
     def add(self, step: int, d: dict) -> None:
         self.steps.append(step)
@@ -71,28 +72,63 @@ class Record:
         """Largest deviations over the run (the columns of Table 2)."""
         return {k + "_max": float(v.max()) for k, v in self.deviations().items()}
 
+    def save(self, stem: str) -> None:
+        """Write the record (``stem``.json) and its maps (``stem``_maps.npz);
+        the particle state is saved separately (``checkpoint``)."""
+        import json
+        with open(stem + ".json", "w") as f:
+            json.dump({"steps": self.steps, "E": self.E, "P": self.P, "Lz": self.Lz, "com": self.com,
+                       "busy_s": self.busy_s, "evals": self.evals}, f)
+        np.savez_compressed(stem + "_maps.npz", **{str(k): v for k, v in self.maps.items()})
+
+    @classmethod
+    def load(cls, stem: str) -> "Record":
+        import json
+        with open(stem + ".json") as f:
+            d = json.load(f)
+        rec = cls(steps=d["steps"], E=d["E"], P=[tuple(p) for p in d["P"]], Lz=d["Lz"],
+                  com=[tuple(c) for c in d["com"]], busy_s=d["busy_s"], evals=d["evals"])
+        with np.load(stem + "_maps.npz", allow_pickle=False) as z:
+            rec.maps = {int(k): z[k] for k in z.files}
+        return rec
+
 
 def run(ctx, ic: dict, prm: "nb.Params", dt: float, steps: int, every: int = 50, maps_at=(),
-        grid: Grid | None = None, plan: dict | None = None, progress=None) -> Record:
+        grid: Grid | None = None, plan: dict | None = None, progress=None, resume=None,
+        stop_at: int | None = None) -> Record:
     """Integrate ``ic`` for ``steps`` leapfrog steps of ``dt``, sampling the
     diagnostics every ``every`` steps (and at 0) and a surface-density map at
     each step count in ``maps_at``.  ``plan`` pins the launch plan of the
-    pair sum for this size (cleared afterwards)."""
+    pair sum for this size (cleared afterwards).
+
+    A run can be cut into pieces: ``stop_at`` ends it early at that step
+    (``Record.done`` tells where), and ``resume=(record, step)`` continues
+    from a record and a state saved at ``step`` (``ic`` then holds that
+    state, accelerations included, as ``checkpoint`` writes it); the pieces
+    take the same steps as one run, bit for bit."""
     grid = grid or Grid()
     s = nb.System.from_arrays(ic)
     n = s.n
     if plan is not None:
         nb.nbody_plan_set(ctx, prm.prec, n, plan)
     try:
-        rec = Record()
         want_maps = sorted(set(int(k) for k in maps_at if 0 <= k <= steps))
-        nb.nbody_accel(ctx, s, prm)
-        rec.add(0, nb.diag_dict(nb.nbody_diag(ctx, s, prm)))
-        if 0 in want_maps:
-            rec.maps[0] = _map(ctx, s, grid)
-        done = 0
+        if resume is None:
+            rec = Record()
+            nb.nbody_accel(ctx, s, prm)
+            rec.add(0, nb.diag_dict(nb.nbody_diag(ctx, s, prm)))
+            if 0 in want_maps:
+                rec.maps[0] = _map(ctx, s, grid)
+            done = 0
+        else:
+            rec, done = resume
+        end = steps if stop_at is None else min(steps, stop_at)
         stops = sorted(set(list(range(every, steps, every)) + [steps] + want_maps) - {0})
         for stop in stops:
+            if stop <= done:
+                continue
+            if stop > end:
+                break
             k = stop - done
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -108,6 +144,7 @@ def run(ctx, ic: dict, prm: "nb.Params", dt: float, steps: int, every: int = 50,
             if progress is not None:
                 progress(done, rec)
         rec.final = s.numpy()
+        rec.done = done
         return rec
     finally:
         if plan is not None:

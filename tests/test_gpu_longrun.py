@@ -49,3 +49,31 @@ def test_fp64_series_match_oracle(nb, ctx, orc):
     g = rec.final
     assert np.max(np.abs(g["x"] - ref["x"])) <= 1e-9
 
+
+
+def test_stop_and_resume_bitwise(nb, ctx, tmp_path):
+    # a run cut in two pieces (state and record saved in between) takes the
+    # same steps as one run, bit for bit
+    from paper_1803_01190_amd import checkpoint
+    from paper_1803_01190_amd import longrun as lr
+    n, steps, every, eps = 1024, 60, 20, 0.02
+    halo = wl.no_halo()
+    dt = wl.outer_period(halo=halo) / 4000.0
+    ic = wl.make("disk_sg", n, 8)
+    prm = nb.Params(eps=eps, prec=nb.NB_MIXED)
+    grid = lr.Grid(32, 32, -6.0, -6.0, 12.0 / 32)
+    whole = lr.run(ctx, ic, prm, dt, steps, every=every, maps_at=(0, 30, 60), grid=grid)
+    first = lr.run(ctx, ic, prm, dt, steps, every=every, maps_at=(0, 30, 60), grid=grid, stop_at=40)
+    assert first.done == 40 and whole.done == steps
+    stem = str(tmp_path / "piece")
+    checkpoint.save(stem + "_state.npz", nb.System.from_arrays(first.final), prm, step=first.done)
+    first.save(stem)
+    st, _, _, step, _ = checkpoint.load(stem + "_state.npz")
+    rest = lr.run(ctx, st.numpy(), prm, dt, steps, every=every, maps_at=(0, 30, 60), grid=grid,
+                  resume=(lr.Record.load(stem), step))
+    assert rest.done == steps and rest.evals == steps and rest.steps == whole.steps
+    assert rest.E == whole.E and rest.Lz == whole.Lz and rest.P == whole.P
+    for k in (0, 30, 60):
+        assert np.array_equal(rest.maps[k], whole.maps[k])
+    for k in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az"):
+        assert np.array_equal(rest.final[k], whole.final[k]), k
