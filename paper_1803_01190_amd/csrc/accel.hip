@@ -76,15 +76,15 @@ struct Lane {
     F tx[R], ty[R], tz[R], tp[R];            // inner sums
     O ox[R], oy[R], oz[R], op[R];            // outer sums (MIXED only)
     // Equal-mass runs (float64): sums of the pair terms without the source
-    // mass, for sources of mass mrun not yet folded into tx.
-    double ux[R], uy[R], uz[R];
+    // mass, for sources of mass mrun not yet folded into tx..tp.
+    double ux[R], uy[R], uz[R], up[R];
     double mrun;
 };
 
-// One source against R targets.  UM (equal-mass run, accelerations only):
-// the source mass is left out of the pair term and applied once to the run's
-// sum (float64: fold(); mixed: the per-tile flush), saving one multiply per
-// pair.
+// One source against R targets.  UM (equal-mass run; the acceleration or
+// the potential alone): the source mass is left out of the pair term and
+// applied once to the run's sum (float64: fold(); mixed: the per-tile
+// flush), saving one multiply per pair.
 // MASK (potential modes, only for the few source groups that can hold one of
 // the workgroup's own targets): bit r of selfbits marks the source as target
 // slot r itself, whose term is left out.  Elsewhere no pair is the self pair,
@@ -93,7 +93,7 @@ template <int PREC, int R, int MODE, bool SAFE, bool UM = false, bool MASK = fal
 __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy, double sz,
                                          double sm, float fx, float fy, float fz, float fm,
                                          double eps2, float eps2f, uint32_t selfbits = 0) {
-    static_assert(!UM || (MODE == MODE_ACC && PREC != P_FP32), "equal-mass runs: fp64/mixed accelerations");
+    static_assert(!UM || (MODE != MODE_ACC_PHI && PREC != P_FP32), "equal-mass runs: fp64/mixed, one output");
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if constexpr (PREC == P_FP64) {
@@ -120,7 +120,8 @@ __device__ __forceinline__ void interact(Lane<PREC, R> &L, double sx, double sy,
             }
             if constexpr (MODE != MODE_ACC) {
                 const double c1 = __builtin_fma(e, __builtin_fma(L.k0375, e, -0.5), 1.0);
-                L.tp[r] = __builtin_fma(sm * y, c1, L.tp[r]);
+                if constexpr (UM) L.up[r] = __builtin_fma(y, c1, L.up[r]);
+                else L.tp[r] = __builtin_fma(sm * y, c1, L.tp[r]);
             }
         } else {
             float dx, dy, dz;
@@ -156,7 +157,8 @@ __device__ __forceinline__ void flush(Lane<PREC, R> &L, bool um = false, double 
                 L.ox[r] = __builtin_fma(m0, (double)L.tx[r], L.ox[r]);
                 L.oy[r] = __builtin_fma(m0, (double)L.ty[r], L.oy[r]);
                 L.oz[r] = __builtin_fma(m0, (double)L.tz[r], L.oz[r]);
-                L.tx[r] = L.ty[r] = L.tz[r] = 0.0f;
+                L.op[r] = __builtin_fma(m0, (double)L.tp[r], L.op[r]);
+                L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0.0f;
             }
         } else {
 #pragma unroll
@@ -169,7 +171,7 @@ __device__ __forceinline__ void flush(Lane<PREC, R> &L, bool um = false, double 
     }
 }
 
-// float64: add the pending equal-mass run, scaled by its mass, into tx.
+// float64: add the pending equal-mass run, scaled by its mass, into tx..tp.
 template <int PREC, int R>
 __device__ __forceinline__ void fold(Lane<PREC, R> &L) {
     if constexpr (PREC == P_FP64) {
@@ -178,7 +180,8 @@ __device__ __forceinline__ void fold(Lane<PREC, R> &L) {
             L.tx[r] = __builtin_fma(L.mrun, L.ux[r], L.tx[r]);
             L.ty[r] = __builtin_fma(L.mrun, L.uy[r], L.ty[r]);
             L.tz[r] = __builtin_fma(L.mrun, L.uz[r], L.tz[r]);
-            L.ux[r] = L.uy[r] = L.uz[r] = 0.0;
+            L.tp[r] = __builtin_fma(L.mrun, L.up[r], L.tp[r]);
+            L.ux[r] = L.uy[r] = L.uz[r] = L.up[r] = 0.0;
         }
     }
 }
@@ -206,7 +209,7 @@ __device__ __forceinline__ void lane_init(Lane<PREC, R> &L, const State &st, int
         L.zi[r] = ok ? (typename Tr<PREC>::Ti)st.z[i] : 0;
         L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0;
         L.ox[r] = L.oy[r] = L.oz[r] = L.op[r] = 0;
-        L.ux[r] = L.uy[r] = L.uz[r] = 0.0;
+        L.ux[r] = L.uy[r] = L.uz[r] = L.up[r] = 0.0;
     }
     L.mrun = 0.0;
 }
@@ -234,7 +237,7 @@ template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
 __device__ __forceinline__ void sweep_lds(Lane<PREC, R> &L, const State &st, int64_t jb,
                                           int64_t je, int64_t ib, double eps2, float eps2f,
                                           typename Tr<PREC>::J *tile) {
-    constexpr bool kUM = MODE == MODE_ACC && PREC != P_FP32;
+    constexpr bool kUM = MODE != MODE_ACC_PHI && PREC != P_FP32;
     const int t = threadIdx.x;
     for (int64_t jt = jb; jt < je; jt += BLOCK) {
         const int64_t j = jt + t;
@@ -378,7 +381,7 @@ template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
 __device__ __forceinline__ void sweep_scalar_any(Lane<PREC, R> &L, const State &st, int64_t jb,
                                                  int64_t je, int64_t ib, double eps2,
                                                  float eps2f) {
-    if constexpr (MODE == MODE_ACC && PREC != P_FP32) {
+    if constexpr (MODE != MODE_ACC_PHI && PREC != P_FP32) {
         if (range_equal_mass<BLOCK>(st.m, jb, je)) {
             L.mrun = st.m[jb];
             sweep_scalar<PREC, R, BLOCK, MODE, SAFE, true>(L, st, jb, je, ib, eps2, eps2f);

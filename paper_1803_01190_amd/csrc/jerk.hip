@@ -27,11 +27,12 @@ namespace nb {
 namespace {
 
 struct alignas(16) SD { double x, y, z, u, v, w, m, pad; };
+struct alignas(16) SX { double x, y, z, u, v, w; float m, pad; };  // mixed: float mass
 struct alignas(16) SF { float x, y, z, u, v, w, m, pad; };
 
 template <int PREC> struct JT;
 template <> struct JT<P_FP64> { using S = SD; using Ti = double; using A = double; };
-template <> struct JT<P_MIXED> { using S = SD; using Ti = double; using A = float; };
+template <> struct JT<P_MIXED> { using S = SX; using Ti = double; using A = float; };
 template <> struct JT<P_FP32> { using S = SF; using Ti = float; using A = float; };
 
 template <int PREC, int R>
@@ -56,7 +57,8 @@ __device__ __forceinline__ typename JT<PREC>::S load_src(const JerkLaunch &J, in
     using T = decltype(e.x);
     e.x = ok ? (T)J.x[j] : T(0); e.y = ok ? (T)J.y[j] : T(0); e.z = ok ? (T)J.z[j] : T(0);
     e.u = ok ? (T)J.vx[j] : T(0); e.v = ok ? (T)J.vy[j] : T(0); e.w = ok ? (T)J.vz[j] : T(0);
-    e.m = ok ? (T)J.m[j] : T(0); e.pad = T(0);
+    using TM = decltype(e.m);
+    e.m = ok ? (TM)J.m[j] : TM(0); e.pad = TM(0);
     return e;
 }
 
@@ -89,7 +91,7 @@ __device__ __forceinline__ void interact(JLane<PREC, R> &L, const typename JT<PR
             if constexpr (PREC == P_MIXED) {
                 dx = (float)(s.x - L.x[r]); dy = (float)(s.y - L.y[r]); dz = (float)(s.z - L.z[r]);
                 du = (float)(s.u - L.u[r]); dv = (float)(s.v - L.v[r]); dw = (float)(s.w - L.w[r]);
-                m = (float)s.m;
+                m = s.m;
             } else {
                 dx = s.x - L.x[r]; dy = s.y - L.y[r]; dz = s.z - L.z[r];
                 du = s.u - L.u[r]; dv = s.v - L.v[r]; dw = s.w - L.w[r];
