@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--precs", default="mixed,fp64,fp32")
     ap.add_argument("--tune-ms", type=float, default=4000.0)
-    ap.add_argument("--sample-rows", type=int, default=8192,
+    ap.add_argument("--sample-rows", type=int, default=32768,
                     help="oracle rows (each summed over all N) for the CPU baseline and force errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plans-in", default=None,

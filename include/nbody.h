@@ -7,9 +7,12 @@
  *       a_i = G sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}
  *   - kick-drift-kick leapfrog, Section 1, Eqs. (5)-(7), one force
  *     evaluation per step;
- *   - a fourth-order scheme (named, not specified, in the abstract): the
- *     triple-jump composition of the leapfrog step, three evaluations per step;
- *   - energy, momentum and angular momentum, Section 3, Eqs. (8)-(10).
+ *   - fourth-order schemes (named, not specified, in the abstract): the
+ *     triple-jump composition of the leapfrog step (three evaluations per
+ *     step), the fourth-order Hermite scheme on an acceleration-and-jerk sum
+ *     (one evaluation per step) and classical Runge-Kutta (four);
+ *   - energy, momentum and angular momentum, Section 3, Eqs. (8)-(10), and
+ *     the surface-density maps of Section 3 (Fig. 7).
  *
  * Conventions shared by every entry point
  *   Memory.   Particle arrays are caller-owned DEVICE memory: contiguous

@@ -8,8 +8,11 @@ through ctypes and shares no code with the GPU library.
 Functions follow the paper (Khrapov, Khoperskov & Khoperskov 2018):
 ``accel`` -- Eqs. (1)-(2); ``step_kdk`` -- Eqs. (5)-(7); ``step_o4`` -- the
 fourth-order scheme named in the abstract (triple-jump composition);
-``diag`` -- Eqs. (8)-(10) plus centre of mass; ``halo_accel`` -- the optional
-fixed external field of the disk workloads (not in the paper).
+``accel_jerk``, ``State.step_hermite``, ``State.step_rk4`` -- the other
+readings of that scheme (fourth-order Hermite on the jerk, classical RK4);
+``diag`` -- Eqs. (8)-(10) plus centre of mass; ``surface_density`` -- the
+maps of Section 3 (Fig. 7); ``halo_accel`` -- the optional fixed external
+field of the disk workloads (not in the paper).
 """
 from __future__ import annotations
 

@@ -23,7 +23,8 @@
  *  - The fixed halo is not in the paper (its disk is fully self-gravitating);
  *    it is an optional external field: a cored isothermal sphere.
  *  - The "fourth-order scheme" of the abstract is not named; the triple-jump
- *    composition of the leapfrog step (Yoshida 1990; Forest & Ruth 1990) is used.
+ *    composition of the leapfrog step (Yoshida 1990; Forest & Ruth 1990) is used,
+ *    and the fourth-order Hermite scheme and classical RK4 are provided too.
  */
 #include <math.h>
 #include <stdint.h>
