@@ -31,7 +31,8 @@ FLOPS_PER_INTERACTION = 20  # conventional count for the softened pair term
 JERK_FLOPS_PER_INTERACTION = 42  # the 20 above + relative velocity (3), r.u (5), factor (2), jerk FMAs (12)
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "fp32": 157.3}  # MI355X vector peaks
 DTYPE = {"fp64": "f64", "mixed": "f32 pair / f64 accumulate+state", "fp32": "f32"}
-KERNEL_SOURCES = ["paper_1803_01190_amd/csrc/accel.hip", "paper_1803_01190_amd/csrc/nbody_internal.h"]
+KERNEL_SOURCES = ["paper_1803_01190_amd/csrc/accel.hip", "paper_1803_01190_amd/csrc/order.hip",
+                  "paper_1803_01190_amd/csrc/nbody_internal.h"]
 
 
 def log(*a):
@@ -281,7 +282,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": r0["achieved_tflops"] / PEAK_TFLOPS[head],
             "traffic": traffic,
-            "kernel": "pair sum (k_pair)",
+            "kernel": ("pair sum in spatial order (k_pair_local, with its ordering kernels)"
+                       if r0["plan"].get("jsrc") == 2 else "pair sum (k_pair)"),
             "flops_per_interaction": FLOPS_PER_INTERACTION,
             "interactions_per_launch": float(n) * float(n),
         },

@@ -486,7 +486,173 @@ __global__ __launch_bounds__(256) void k_pair_reduce(PairLaunch P) {
             sx += b[0]; sy += b[rows]; sz += b[2 * rows]; sp += b[3 * rows];
         }
     }
-    finish<PREC, MODE>(P.st, P.sc, P.i0 + q, sx, sy, sz, sp, P.kick, P.hdt);
+    // rows are sorted positions under a spatially ordered (jsrc = 2) plan
+    const int64_t i = P.lo.perm ? (int64_t)P.lo.perm[P.i0 + q] : P.i0 + q;
+    finish<PREC, MODE>(P.st, P.sc, i, sx, sy, sz, sp, P.kick, P.hdt);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision with tile-local coordinates (jsrc = 2).  The system is
+// taken in a spatial order (order.hip): targets and sources are its
+// particles sorted along a Morton curve, and each tile of 256 sorted sources
+// has a bounding box.  For a source tile whose box is farther from the
+// workgroup's targets' box than its own diagonal, positions are taken
+// relative to the tile's centre c: each source stores fl32(x_j - c) once per
+// tile, each target forms fl32(x_i - c) once per tile, and the pair
+// separation is one float32 subtraction of the two.  Both rounding errors
+// are at most u (|x_j - c| + |x_i - c|) <= u (diagonal + distance), and the
+// distance exceeds the diagonal, so the separation keeps a relative error of
+// a few u, as the float64 difference rounded to float32 does; it costs one
+// float32 subtraction per coordinate instead of a float64 subtraction and a
+// conversion.  Nearer tiles take the mixed pair term of the other plans.
+struct alignas(16) JL { float x, y, z, m; };  // tile-local float32 source
+
+template <int R, bool SAFE, bool UM>
+__device__ __forceinline__ void interact_local(Lane<P_MIXED, R> &L, const JL &e, const float *rx,
+                                               const float *ry, const float *rz, float eps2f) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float dx = e.x - rx[r], dy = e.y - ry[r], dz = e.z - rz[r];
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        float y = __builtin_amdgcn_rsqf(r2);
+        if constexpr (SAFE) y = (r2 >= kMinNormal32) ? y : 0.0f;
+        const float my = UM ? y : e.m * y;
+        const float sc = my * (y * y);
+        L.tx[r] = __builtin_fmaf(sc, dx, L.tx[r]);
+        L.ty[r] = __builtin_fmaf(sc, dy, L.ty[r]);
+        L.tz[r] = __builtin_fmaf(sc, dz, L.tz[r]);
+    }
+}
+
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk) {
+    constexpr int BLOCK = 256;
+    __shared__ JL ftile[BLOCK];
+    __shared__ JM dtile[BLOCK];
+    const LocalOrder &O = P.lo;
+    const int64_t n = P.sc.n;
+    const int64_t ib = (int64_t)blockIdx.x * (BLOCK * R);  // sorted positions, all n targets
+    const int64_t jb = (int64_t)blockIdx.y * chunk;
+    const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+    const int t = threadIdx.x;
+    State sv{};  // the sorted positions and masses, read-only
+    sv.x = const_cast<double *>(O.px);
+    sv.y = const_cast<double *>(O.py);
+    sv.z = const_cast<double *>(O.pz);
+    sv.m = O.pm;
+    Lane<P_MIXED, R> L;
+    lane_init<P_MIXED, R>(L, sv, ib, n, BLOCK);
+    // box of this workgroup's targets: the boxes of its R tiles
+    const int64_t ntile = (n + BLOCK - 1) / BLOCK;
+    double bmin[3] = {1.0e308, 1.0e308, 1.0e308}, bmax[3] = {-1.0e308, -1.0e308, -1.0e308};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t tt = ib / BLOCK + r;
+        if (tt < ntile) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bmin[c] = fmin(bmin[c], O.tbox[6 * tt + c]);
+                bmax[c] = fmax(bmax[c], O.tbox[6 * tt + 3 + c]);
+            }
+        }
+    }
+    for (int64_t jt = jb; jt < je; jt += BLOCK) {
+        const double *tb = O.tbox + 6 * (jt / BLOCK);
+        double gap2 = 0.0, diag2 = 0.0, ctr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double lo = tb[c], hi = tb[3 + c];
+            const double g = fmax(0.0, fmax(lo - bmax[c], bmin[c] - hi));
+            gap2 += g * g;
+            diag2 += (hi - lo) * (hi - lo);
+            ctr[c] = 0.5 * (lo + hi);
+        }
+        const int64_t j = jt + t;
+        const bool ok = j < je;
+        if (gap2 > diag2) {  // far tile (a uniform branch)
+            JL e;
+            e.x = ok ? (float)(O.px[j] - ctr[0]) : 0.0f;
+            e.y = ok ? (float)(O.py[j] - ctr[1]) : 0.0f;
+            e.z = ok ? (float)(O.pz[j] - ctr[2]) : 0.0f;
+            e.m = ok ? (float)O.pm[j] : 0.0f;
+            ftile[t] = e;
+            __syncthreads();
+            float rx[R], ry[R], rz[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                rx[r] = (float)(L.xi[r] - ctr[0]);
+                ry[r] = (float)(L.yi[r] - ctr[1]);
+                rz[r] = (float)(L.zi[r] - ctr[2]);
+            }
+            const float m0 = ftile[0].m;
+            const bool um = __syncthreads_and(e.m == m0) != 0;
+            if (um) {
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k) interact_local<R, SAFE, true>(L, ftile[k], rx, ry, rz, P.sc.eps2f);
+            } else {
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k) interact_local<R, SAFE, false>(L, ftile[k], rx, ry, rz, P.sc.eps2f);
+            }
+            flush(L, um, (double)m0);
+        } else {
+            const JM e = load_src<P_MIXED>(sv, j, ok);
+            dtile[t] = e;
+            __syncthreads();
+            const double m0 = (double)dtile[0].m;
+            const bool um = __syncthreads_and((double)e.m == m0) != 0;
+            if (um) {
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k) {
+                    const JM &f = dtile[k];
+                    interact<P_MIXED, R, MODE_ACC, SAFE, true>(L, f.x, f.y, f.z, 0, 0, 0, 0, 0, P.sc.eps2,
+                                                                P.sc.eps2f);
+                }
+            } else {
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k) interact_src<P_MIXED, R, MODE_ACC, SAFE>(L, dtile[k], P.sc.eps2, P.sc.eps2f);
+            }
+            flush(L, um, m0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = ib + (int64_t)r * BLOCK + t;
+        if (i >= n) continue;
+        double sx, sy, sz, sp;
+        raw<P_MIXED, R>(L, r, sx, sy, sz, sp);
+        if (P.split > 1) {
+            double *q = P.part + (int64_t)blockIdx.y * 4 * n + i;
+            q[0] = sx; q[n] = sy; q[2 * n] = sz; q[3 * n] = sp;
+        } else {
+            finish<P_MIXED, MODE_ACC>(P.st, P.sc, O.perm[i], sx, sy, sz, sp, P.kick, P.hdt);
+        }
+    }
+}
+
+template <int R>
+hipError_t go_local(const PairLaunch &P, hipStream_t s) {
+    const int64_t n = P.sc.n;
+    const int64_t per = 256LL * R;
+    const int64_t nbx = (n + per - 1) / per;
+    const int64_t per_chunk = (n + P.split - 1) / P.split;
+    const int64_t chunk = ((per_chunk + 255) / 256) * 256;
+    if (nbx <= 0) return hipSuccess;
+    dim3 grid((unsigned)nbx, (unsigned)P.split);
+    if (P.sc.safe32)
+        hipLaunchKernelGGL((k_pair_local<R, true>), grid, dim3(256), 0, s, P, chunk);
+    else
+        hipLaunchKernelGGL((k_pair_local<R, false>), grid, dim3(256), 0, s, P, chunk);
+    return hipGetLastError();
+}
+
+hipError_t pick_local(const PairLaunch &P, hipStream_t s) {
+    if (P.sc.prec != P_MIXED || P.mode != MODE_ACC || P.block != 256 || P.i0 != 0 || P.i1 != P.sc.n ||
+        !P.lo.perm)
+        return hipErrorInvalidValue;
+    if (P.R == 1) return go_local<1>(P, s);
+    if (P.R == 2) return go_local<2>(P, s);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -638,12 +804,14 @@ int pair_batched_occupancy(int prec, int R, int block, int mode) {
 }
 
 bool pair_config_supported(int prec, int R, int block, int jsrc, int mode) {
+    if (jsrc == 2) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
     if (prec < 0 || prec > 2 || (jsrc != 0 && jsrc != 1)) return false;
     if (mode != MODE_ACC) return block == 256 && (R == 1 || R == 2);
     return (block == 128 || block == 256) && (R == 1 || R == 2 || R == 4);
 }
 
 hipError_t launch_pair(const PairLaunch &P, hipStream_t s) {
+    if (P.jsrc == 2) return pick_local(P, s);
     switch (P.sc.prec) {
         case P_FP64: return pick_mode<P_FP64>(P, s);
         case P_MIXED: return pick_mode<P_MIXED>(P, s);

@@ -38,6 +38,15 @@ struct State {
     double *vx, *vy, *vz;
 };
 
+// Spatial order of one system (jsrc = 2 plans): particles sorted along a
+// Morton curve, their positions and masses in that order, and a bounding box
+// (min x, y, z, max x, y, z) per tile of 256 sorted particles.
+struct LocalOrder {
+    const int32_t *perm;                   // sorted position -> particle index
+    const double *px, *py, *pz, *pm;
+    const double *tbox;
+};
+
 // One single-system pair-sum launch: targets [i0, i1), sources [0, n).
 struct PairLaunch {
     State st;
@@ -47,6 +56,7 @@ struct PairLaunch {
     double hdt;        // > 0 (or != 0): fuse the closing half kick v += hdt a
     int32_t kick;
     double *part;      // split > 1: [split][4][i1 - i0] partial sums
+    LocalOrder lo;     // jsrc = 2 only; rows are then sorted positions
 };
 
 // One work item of a batched launch: a tile of targets of one system.
@@ -91,7 +101,6 @@ hipError_t launch_kick_batched(const State &st, const int64_t *off_dev, const Sy
 hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst *sys,
                               int32_t B, double *out, hipStream_t s);
 
-// Small utilities.
 // Acceleration and jerk pair sum (fourth-order Hermite).  The sum is
 // evaluated at (x, v); without corr it stores a and j, with corr it applies
 // the Hermite corrector to the current state (x0, v0, and a, j as a0, j0)
@@ -126,11 +135,15 @@ struct RK4Launch {
 };
 
 hipError_t launch_pair_jerk(const JerkLaunch &J, hipStream_t s);
+// bytes of scratch launch_local_order needs for n particles
+size_t local_order_bytes(int64_t n);
+hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOrder *out, hipStream_t s);
 hipError_t launch_hermite_predict(const HermitePredict &H, int fp32, hipStream_t s);
 hipError_t launch_rk4(const RK4Launch &K, int fp32, hipStream_t s);
 hipError_t launch_surface_density(const double *x, const double *y, int64_t n, int32_t nx, int32_t ny,
                                   double x0, double y0, double sx, double sy, uint32_t *counts,
                                   hipStream_t s);
+// Small utilities.
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // write one SysConst into device memory (graph-capturable, no host staging)
 hipError_t launch_set_sysconst(SysConst *dst, const SysConst &v, hipStream_t s);

@@ -39,6 +39,8 @@ struct nbody_ctx {
     size_t phi_cap = 0;    // doubles
     double *integ = nullptr;  // Hermite predicted state / RK4 stages
     size_t integ_cap = 0;     // doubles
+    double *order = nullptr;  // spatial order of a system (jsrc 2 plans)
+    size_t order_cap = 0;     // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
     // Scratch outgrown by a larger call is kept (not freed) until the
     // context is destroyed: a HIP graph captured earlier may still use it,
@@ -268,6 +270,19 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
     P.hdt = hdt;
     if (!pair_config_supported(sc.prec, P.R, P.block, P.jsrc, mode))
         return fail(ctx, NB_ENOTSUP, "unsupported plan R=%d block=%d jsrc=%d for mode %d", P.R, P.block, P.jsrc, mode);
+    if (P.jsrc == 2) {
+        if (i0 != 0 || i1 != sc.n)
+            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2) sums whole systems only");
+        if (capturing(s)) {
+            // the ordering uses a library sort; under stream capture the
+            // plan runs with LDS source tiles in the particles' own order
+            nbody_plan p0 = pl;
+            p0.jsrc = 0;
+            return run_pair(ctx, st, sc, i0, i1, mode, p0, kick, hdt, s);
+        }
+        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(sc.n) + 7) / 8);
+        if (r != NB_OK) return r;
+    }
     if (P.split > 1) {
         const size_t need = (size_t)P.split * 4 * (size_t)(i1 - i0);
         nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, need);
@@ -275,6 +290,10 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
         P.part = ctx->part;
     }
     Timed t(ctx, s, 0, (i1 - i0) * sc.n);
+    if (P.jsrc == 2) {
+        const hipError_t eo = launch_local_order(st, sc.n, ctx->order, &P.lo, s);
+        if (eo != hipSuccess) return hipfail(ctx, eo, "spatial order");
+    }
     hipError_t e = launch_pair(P, s);
     if (e != hipSuccess) return hipfail(ctx, e, "pair-sum launch");
     if (P.split > 1) {
@@ -483,6 +502,7 @@ nbody_status nbody_ctx_destroy(nbody_ctx *ctx) {
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->phi) (void)hipFree(ctx->phi);
     if (ctx->integ) (void)hipFree(ctx->integ);
+    if (ctx->order) (void)hipFree(ctx->order);
     for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->sysc) (void)hipFree(ctx->sysc);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);

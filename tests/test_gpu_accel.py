@@ -228,3 +228,75 @@ def test_mass_patterns(nb, ctx, orc, prec, jsrc, pattern):
     tol = {"eps_rms": FP64_TOL, "eps_cond": FP64_TOL} if prec == "fp64" else MIXED_TOL
     for k, v in tol.items():
         assert e[k] <= v, (prec, jsrc, pattern, e)
+
+
+LOCAL_PLANS = [dict(R=R, block=256, split=s, jsrc=2) for R in (1, 2) for s in (1, 3)]
+
+
+@pytest.mark.parametrize("plan", LOCAL_PLANS, ids=lambda p: f"R{p['R']}s{p['split']}")
+@pytest.mark.parametrize("model,n", [("plummer", 4099), ("disk", 20000), ("plummer", 300)])
+def test_mixed_tile_local(nb, ctx, orc, plan, model, n):
+    # mixed precision with tile-local float32 coordinates for far source
+    # tiles (spatially ordered plan): the same gate as the other mixed plans
+    print(f"[case] mixed local {model} n={n} plan={plan}", flush=True)
+    ic = wl.make(model, n, 60 + n % 11)
+    eps = 0.02 if model == "disk" else 0.01
+    halo = wl.default_halo() if model == "disk" else None
+    ref, _, A = oracle_accel(orc, ic, eps, halo=halo)
+    got = run_accel(nb, ctx, ic, eps, nb.NB_MIXED, halo=halo, plan=plan)
+    e = errs(got, ref, A)
+    for k, v in MIXED_TOL.items():
+        assert e[k] <= v, (model, n, plan, e)
+    # and close to the mixed plans that form every separation in float64
+    std = run_accel(nb, ctx, ic, eps, nb.NB_MIXED, halo=halo, plan=dict(R=2, block=256, split=1, jsrc=0))
+    e2 = errs(got, np.stack([std["ax"], std["ay"], std["az"]]), A)
+    assert e2["eps_cond"] <= 2e-5, e2
+
+
+def test_mixed_tile_local_edges(nb, ctx, orc):
+    plan = dict(R=2, block=256, split=2, jsrc=2)
+    # eps = 0 with coincident particles; a far translation; unequal masses
+    ic = wl.plummer(3000, 61)
+    for k in ("x", "y", "z"):
+        ic[k][5] = ic[k][6]
+    ic["m"] = ic["m"] * (1.0 + 0.5 * np.sin(np.arange(3000)))
+    ref, _, A = oracle_accel(orc, ic, 0.0)
+    got = run_accel(nb, ctx, ic, 0.0, nb.NB_MIXED, plan=plan)
+    assert all(np.all(np.isfinite(got[k])) for k in ("ax", "ay", "az"))
+    assert errs(got, ref, A)["eps_cond"] <= MIXED_TOL["eps_cond"]
+    sh = dict(ic)
+    sh["x"] = ic["x"] + 1000.0
+    ref2, _, A2 = oracle_accel(orc, ic, 0.01)
+    got2 = run_accel(nb, ctx, sh, 0.01, nb.NB_MIXED, plan=plan)
+    assert errs(got2, ref2, A2)["eps_cond"] <= MIXED_TOL["eps_cond"]
+    # a spatially ordered plan sums whole systems only
+    s = nb.System.from_arrays(wl.plummer(2000, 62))
+    nb.nbody_plan_set(ctx, nb.NB_MIXED, 2000, plan)
+    try:
+        with pytest.raises(nb.NBodyError) as ei:
+            nb.nbody_accel_rows(ctx, s, nb.Params(eps=0.01, prec=nb.NB_MIXED), 10, 500)
+        assert ei.value.status == nb.NB_ENOTSUP
+        nb.nbody_accel_rows(ctx, s, nb.Params(eps=0.01, prec=nb.NB_MIXED), 0, 2000)
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, 2000, None)
+
+
+def test_mixed_tile_local_steps_deterministic(nb, ctx):
+    # the spatial order is recomputed every evaluation and is deterministic
+    plan = dict(R=2, block=256, split=4, jsrc=2)
+    ic = wl.exp_disk(30000, 63)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    out = []
+    nb.nbody_plan_set(ctx, nb.NB_MIXED, 30000, plan)
+    try:
+        for _ in range(2):
+            s = nb.System.from_arrays(ic)
+            nb.nbody_accel(ctx, s, prm)
+            nb.nbody_step_kdk(ctx, s, prm, 1e-3, 5)
+            torch.cuda.synchronize()
+            out.append(s.numpy())
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, 30000, None)
+    for k in ("x", "vx", "ax"):
+        assert np.array_equal(out[0][k], out[1][k]), k
