@@ -134,7 +134,11 @@ typedef struct {
  *         order (>= 1; small systems use it to fill the GPU; ignored, i.e. 1,
  *         for NB_FP32)
  *   jsrc  0 = j tiles staged through LDS, 1 = j read through the scalar
- *         cache straight into SGPR operands */
+ *         cache straight into SGPR operands, 2 = NB_MIXED accelerations in a
+ *         spatial (Morton) order: far source tiles use float32 coordinates
+ *         relative to the tile's centre (256 lanes, R = 1 or 2, whole
+ *         system only: nbody_accel_rows returns NB_ENOTSUP; a stream
+ *         capture runs the plan as jsrc 0) */
 typedef struct {
     int32_t R;
     int32_t block;
