@@ -283,7 +283,7 @@ def main():
             "frac": r0["achieved_tflops"] / PEAK_TFLOPS[head],
             "traffic": traffic,
             "kernel": ("pair sum in spatial order (k_pair_local, with its ordering kernels)"
-                       if r0["plan"].get("jsrc") == 2 else "pair sum (k_pair)"),
+                       if r0["plan"].get("jsrc") in (2, 3) else "pair sum (k_pair)"),
             "flops_per_interaction": FLOPS_PER_INTERACTION,
             "interactions_per_launch": float(n) * float(n),
         },

@@ -74,7 +74,10 @@ typedef enum {
  *             refined (first-order binomial step on y^3, leaving a one-signed
  *             error below 2.1e-14 per pair term, under the float64 sum's).
  *   NB_MIXED: pair separations formed in float64 from the float64 positions
- *             and then rounded to float32; the pair term in float32; per-target
+ *             and then rounded to float32 (plans with jsrc 2 or 3: for source
+ *             tiles far from the targets, from float32 coordinates relative to
+ *             the tile's centre, with a few u of relative error, u = 2^-24);
+ *             the pair term in float32; per-target
  *             sums in float32 over one j tile, then added into float64
  *             accumulators.  State updates and diagnostics stay float64.
  *   NB_FP32:  the paper's single precision: positions rounded to float32,
@@ -134,10 +137,11 @@ typedef struct {
  *         order (>= 1; small systems use it to fill the GPU; ignored, i.e. 1,
  *         for NB_FP32)
  *   jsrc  0 = j tiles staged through LDS, 1 = j read through the scalar
- *         cache straight into SGPR operands, 2 = NB_MIXED accelerations in a
- *         spatial (Morton) order: far source tiles use float32 coordinates
- *         relative to the tile's centre (256 lanes, R = 1 or 2, whole
- *         system only: nbody_accel_rows returns NB_ENOTSUP; a stream
+ *         cache straight into SGPR operands, 2 and 3 = NB_MIXED accelerations
+ *         in a spatial (Morton) order: far source tiles use float32
+ *         coordinates relative to the tile's centre, subtracted per pair (2)
+ *         or through the expanded squared distance (3) (256 lanes, R = 1 or
+ *         2, whole system only: nbody_accel_rows returns NB_ENOTSUP; a stream
  *         capture runs the plan as jsrc 0) */
 typedef struct {
     int32_t R;

@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_pair_reduce(PairLaunch P) {
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision with tile-local coordinates (jsrc = 2).  The system is
+// Mixed precision with tile-local coordinates (jsrc = 2, and 3 below).  The system is
 // taken in a spatial order (order.hip): targets and sources are its
 // particles sorted along a Morton curve, and each tile of 256 sorted sources
 // has a bounding box.  For a source tile whose box is farther from the
@@ -506,6 +506,56 @@ __global__ __launch_bounds__(256) void k_pair_reduce(PairLaunch P) {
 // float32 subtraction per coordinate instead of a float64 subtraction and a
 // conversion.  Nearer tiles take the mixed pair term of the other plans.
 struct alignas(16) JL { float x, y, z, m; };  // tile-local float32 source
+
+// Expanded far-tile form (jsrc = 3).  With primed coordinates relative to the
+// tile's centre, |x_j' - x_i'|^2 = q_j + q_i - 2 x_i'.x_j' (q = |x'|^2, q_i also
+// carrying the softening), and sum_j s_j (x_j' - x_i') = sum_j s_j x_j' -
+// x_i' sum_j s_j.  Per pair this takes one addition and three fused
+// multiply-adds for the softened squared distance, three fused multiply-adds
+// and one addition for the sums; the term x_i' sum_j s_j is applied once per
+// tile in float64.  Every magnitude involved is at most a small multiple of
+// the squared distance (|x_i'| <= r + diag / 2 and |x_j'| <= diag / 2 < r / 2),
+// so the rounding errors stay a small multiple of u relative to the pair
+// term, as in the subtracted form.  e.x, e.y, e.z: x_j'; e.m holds q_j.
+template <int R, bool SAFE, bool UM>
+__device__ __forceinline__ void interact_expanded(Lane<P_MIXED, R> &L, const JL &e, float fm, const float *wx,
+                                                  const float *wy, const float *wz, const float *qi) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        // wx = -2 x_i' etc.
+        const float r2 = __builtin_fmaf(e.x, wx[r], __builtin_fmaf(e.y, wy[r], __builtin_fmaf(e.z, wz[r], e.m + qi[r])));
+        float y = __builtin_amdgcn_rsqf(r2);
+        if constexpr (SAFE) y = (r2 >= kMinNormal32) ? y : 0.0f;
+        const float my = UM ? y : fm * y;
+        const float sc = my * (y * y);
+        L.tx[r] = __builtin_fmaf(sc, e.x, L.tx[r]);
+        L.ty[r] = __builtin_fmaf(sc, e.y, L.ty[r]);
+        L.tz[r] = __builtin_fmaf(sc, e.z, L.tz[r]);
+        L.tp[r] += sc;  // sum of the pair scales
+    }
+}
+
+// End of an expanded far tile: subtract x_i' times the sum of the scales,
+// then add into the float64 sums (scaled by the tile's mass for an
+// equal-mass tile).
+template <int R>
+__device__ __forceinline__ void flush_expanded(Lane<P_MIXED, R> &L, bool um, double m0, const double *ctr) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double s = (double)L.tp[r];
+        const double fx = __builtin_fma(ctr[0] - L.xi[r], s, (double)L.tx[r]);
+        const double fy = __builtin_fma(ctr[1] - L.yi[r], s, (double)L.ty[r]);
+        const double fz = __builtin_fma(ctr[2] - L.zi[r], s, (double)L.tz[r]);
+        if (um) {
+            L.ox[r] = __builtin_fma(m0, fx, L.ox[r]);
+            L.oy[r] = __builtin_fma(m0, fy, L.oy[r]);
+            L.oz[r] = __builtin_fma(m0, fz, L.oz[r]);
+        } else {
+            L.ox[r] += fx; L.oy[r] += fy; L.oz[r] += fz;
+        }
+        L.tx[r] = L.ty[r] = L.tz[r] = L.tp[r] = 0.0f;
+    }
+}
 
 template <int R, bool SAFE, bool UM>
 __device__ __forceinline__ void interact_local(Lane<P_MIXED, R> &L, const JL &e, const float *rx,
@@ -524,11 +574,12 @@ __device__ __forceinline__ void interact_local(Lane<P_MIXED, R> &L, const JL &e,
     }
 }
 
-template <int R, bool SAFE>
+template <int R, bool SAFE, bool EXP>
 __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk) {
     constexpr int BLOCK = 256;
     __shared__ JL ftile[BLOCK];
     __shared__ JM dtile[BLOCK];
+    __shared__ float fmass[EXP ? BLOCK : 1];
     const LocalOrder &O = P.lo;
     const int64_t n = P.sc.n;
     const int64_t ib = (int64_t)blockIdx.x * (BLOCK * R);  // sorted positions, all n targets
@@ -569,7 +620,35 @@ __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk)
         }
         const int64_t j = jt + t;
         const bool ok = j < je;
-        if (gap2 > diag2) {  // far tile (a uniform branch)
+        if (EXP && gap2 > diag2) {  // far tile, expanded form (a uniform branch)
+            JL e{0.0f, 0.0f, 0.0f, 0.0f};
+            const double mj = ok ? O.pm[j] : 0.0;
+            if (ok) {
+                const double dx = O.px[j] - ctr[0], dy = O.py[j] - ctr[1], dz = O.pz[j] - ctr[2];
+                e.x = (float)dx; e.y = (float)dy; e.z = (float)dz;
+                e.m = (float)(dx * dx + dy * dy + dz * dz);
+            }
+            ftile[t] = e;
+            fmass[t] = (float)mj;
+            float wx[R], wy[R], wz[R], qi[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double dx = L.xi[r] - ctr[0], dy = L.yi[r] - ctr[1], dz = L.zi[r] - ctr[2];
+                wx[r] = (float)(-2.0 * dx); wy[r] = (float)(-2.0 * dy); wz[r] = (float)(-2.0 * dz);
+                qi[r] = (float)(dx * dx + dy * dy + dz * dz + P.sc.eps2);
+            }
+            const double m0 = O.pm[jt];
+            const bool um = __syncthreads_and(mj == m0) != 0;
+            if (um) {
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k) interact_expanded<R, SAFE, true>(L, ftile[k], 0.0f, wx, wy, wz, qi);
+            } else {
+#pragma unroll 4
+                for (int k = 0; k < BLOCK; ++k)
+                    interact_expanded<R, SAFE, false>(L, ftile[k], fmass[k], wx, wy, wz, qi);
+            }
+            flush_expanded(L, um, m0, ctr);
+        } else if (!EXP && gap2 > diag2) {  // far tile (a uniform branch)
             JL e;
             e.x = ok ? (float)(O.px[j] - ctr[0]) : 0.0f;
             e.y = ok ? (float)(O.py[j] - ctr[1]) : 0.0f;
@@ -630,7 +709,7 @@ __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk)
     }
 }
 
-template <int R>
+template <int R, bool EXP>
 hipError_t go_local(const PairLaunch &P, hipStream_t s) {
     const int64_t n = P.sc.n;
     const int64_t per = 256LL * R;
@@ -640,9 +719,9 @@ hipError_t go_local(const PairLaunch &P, hipStream_t s) {
     if (nbx <= 0) return hipSuccess;
     dim3 grid((unsigned)nbx, (unsigned)P.split);
     if (P.sc.safe32)
-        hipLaunchKernelGGL((k_pair_local<R, true>), grid, dim3(256), 0, s, P, chunk);
+        hipLaunchKernelGGL((k_pair_local<R, true, EXP>), grid, dim3(256), 0, s, P, chunk);
     else
-        hipLaunchKernelGGL((k_pair_local<R, false>), grid, dim3(256), 0, s, P, chunk);
+        hipLaunchKernelGGL((k_pair_local<R, false, EXP>), grid, dim3(256), 0, s, P, chunk);
     return hipGetLastError();
 }
 
@@ -650,8 +729,9 @@ hipError_t pick_local(const PairLaunch &P, hipStream_t s) {
     if (P.sc.prec != P_MIXED || P.mode != MODE_ACC || P.block != 256 || P.i0 != 0 || P.i1 != P.sc.n ||
         !P.lo.perm)
         return hipErrorInvalidValue;
-    if (P.R == 1) return go_local<1>(P, s);
-    if (P.R == 2) return go_local<2>(P, s);
+    const bool exp = P.jsrc == 3;
+    if (P.R == 1) return exp ? go_local<1, true>(P, s) : go_local<1, false>(P, s);
+    if (P.R == 2) return exp ? go_local<2, true>(P, s) : go_local<2, false>(P, s);
     return hipErrorInvalidValue;
 }
 
@@ -804,14 +884,14 @@ int pair_batched_occupancy(int prec, int R, int block, int mode) {
 }
 
 bool pair_config_supported(int prec, int R, int block, int jsrc, int mode) {
-    if (jsrc == 2) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
+    if (jsrc == 2 || jsrc == 3) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
     if (prec < 0 || prec > 2 || (jsrc != 0 && jsrc != 1)) return false;
     if (mode != MODE_ACC) return block == 256 && (R == 1 || R == 2);
     return (block == 128 || block == 256) && (R == 1 || R == 2 || R == 4);
 }
 
 hipError_t launch_pair(const PairLaunch &P, hipStream_t s) {
-    if (P.jsrc == 2) return pick_local(P, s);
+    if (P.jsrc == 2 || P.jsrc == 3) return pick_local(P, s);
     switch (P.sc.prec) {
         case P_FP64: return pick_mode<P_FP64>(P, s);
         case P_MIXED: return pick_mode<P_MIXED>(P, s);

@@ -39,7 +39,7 @@ struct nbody_ctx {
     size_t phi_cap = 0;    // doubles
     double *integ = nullptr;  // Hermite predicted state / RK4 stages
     size_t integ_cap = 0;     // doubles
-    double *order = nullptr;  // spatial order of a system (jsrc 2 plans)
+    double *order = nullptr;  // spatial order of a system (jsrc 2 and 3 plans)
     size_t order_cap = 0;     // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
     // Scratch outgrown by a larger call is kept (not freed) until the
@@ -270,9 +270,9 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
     P.hdt = hdt;
     if (!pair_config_supported(sc.prec, P.R, P.block, P.jsrc, mode))
         return fail(ctx, NB_ENOTSUP, "unsupported plan R=%d block=%d jsrc=%d for mode %d", P.R, P.block, P.jsrc, mode);
-    if (P.jsrc == 2) {
+    if (P.jsrc >= 2) {
         if (i0 != 0 || i1 != sc.n)
-            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2) sums whole systems only");
+            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2 or 3) sums whole systems only");
         if (capturing(s)) {
             // the ordering uses a library sort; under stream capture the
             // plan runs with LDS source tiles in the particles' own order
@@ -290,7 +290,7 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
         P.part = ctx->part;
     }
     Timed t(ctx, s, 0, (i1 - i0) * sc.n);
-    if (P.jsrc == 2) {
+    if (P.jsrc >= 2) {
         const hipError_t eo = launch_local_order(st, sc.n, ctx->order, &P.lo, s);
         if (eo != hipSuccess) return hipfail(ctx, eo, "spatial order");
     }

@@ -230,10 +230,12 @@ def test_mass_patterns(nb, ctx, orc, prec, jsrc, pattern):
         assert e[k] <= v, (prec, jsrc, pattern, e)
 
 
-LOCAL_PLANS = [dict(R=R, block=256, split=s, jsrc=2) for R in (1, 2) for s in (1, 3)]
+# jsrc 2: far tiles subtract tile-local coordinates; jsrc 3: far tiles use the
+# expanded squared distance and the per-tile sum of the pair scales
+LOCAL_PLANS = [dict(R=R, block=256, split=s, jsrc=j) for j in (2, 3) for R in (1, 2) for s in (1, 3)]
 
 
-@pytest.mark.parametrize("plan", LOCAL_PLANS, ids=lambda p: f"R{p['R']}s{p['split']}")
+@pytest.mark.parametrize("plan", LOCAL_PLANS, ids=lambda p: f"R{p['R']}s{p['split']}j{p['jsrc']}")
 @pytest.mark.parametrize("model,n", [("plummer", 4099), ("disk", 20000), ("plummer", 300)])
 def test_mixed_tile_local(nb, ctx, orc, plan, model, n):
     # mixed precision with tile-local float32 coordinates for far source
@@ -253,8 +255,10 @@ def test_mixed_tile_local(nb, ctx, orc, plan, model, n):
     assert e2["eps_cond"] <= 2e-5, e2
 
 
-def test_mixed_tile_local_edges(nb, ctx, orc):
-    plan = dict(R=2, block=256, split=2, jsrc=2)
+@pytest.mark.parametrize("jsrc", [2, 3])
+def test_mixed_tile_local_edges(nb, ctx, orc, jsrc):
+    print(f"[case] mixed local edges jsrc={jsrc}", flush=True)
+    plan = dict(R=2, block=256, split=2, jsrc=jsrc)
     # eps = 0 with coincident particles; a far translation; unequal masses
     ic = wl.plummer(3000, 61)
     for k in ("x", "y", "z"):
@@ -281,9 +285,11 @@ def test_mixed_tile_local_edges(nb, ctx, orc):
         nb.nbody_plan_set(ctx, nb.NB_MIXED, 2000, None)
 
 
-def test_mixed_tile_local_steps_deterministic(nb, ctx):
+@pytest.mark.parametrize("jsrc", [2, 3])
+def test_mixed_tile_local_steps_deterministic(nb, ctx, jsrc):
     # the spatial order is recomputed every evaluation and is deterministic
-    plan = dict(R=2, block=256, split=4, jsrc=2)
+    print(f"[case] mixed local deterministic jsrc={jsrc}", flush=True)
+    plan = dict(R=2, block=256, split=4, jsrc=jsrc)
     ic = wl.exp_disk(30000, 63)
     h = wl.default_halo()
     prm = nb.Params(eps=0.02, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)

@@ -3,11 +3,11 @@ launch configuration the benchmark times (plans from tuned_plans.json),
 checked on rows the oracle computes one by one (each summed over all N
 sources), plus the N = 2^17 disk with both integrators.
 
-Stated errors (measured on 32768 rows of this workload): mixed with the
-tuned tile-local plan eps_rms 5.2e-8 / eps_cond 4.7e-8 (its far-tile
-separations carry up to a few u of relative error, against u/2 when every
-separation is a rounded float64 difference, which gives 1.8e-8), gated at
-2e-7; fp32 eps_rms 4.9e-4 / eps_cond 8.0e-4, gated at 2e-3; fp64 gated at
+Stated errors (measured on sampled rows of this workload): mixed with the
+tuned tile-local plans eps_rms 5.2e-8 to 5.4e-8 / eps_cond 4.2e-8 to 4.7e-8
+(their far-tile separations carry up to a few u of relative error, against
+u/2 when every separation is a rounded float64 difference, which gives
+1.8e-8), gated at 2e-7; fp32 eps_rms 4.9e-4 / eps_cond 8.0e-4, gated at 2e-3; fp64 gated at
 1e-12.
 """
 import numpy as np
