@@ -319,7 +319,11 @@ NBODY_API nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, c
 /* Time every candidate plan on synthetic particles of size n on `device`
  * scratch memory, pin the fastest for the key of (prec, n) and return it.
  * Synchronous.  budget_ms > 0 bounds the time spent (at least one
- * candidate is always timed). */
+ * candidate is always timed).  Candidates are the jsrc 0 and 1 plans plus
+ * the key's current plan; above n = 32768 the candidates sweep only the
+ * first 32768 sources, so a current spatially ordered plan (jsrc 2 or 3,
+ * whose speed also depends on how the particles are distributed) is not
+ * timed there and the result is a jsrc 0 or 1 plan. */
 NBODY_API nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms,
                             nbody_plan *out);
 

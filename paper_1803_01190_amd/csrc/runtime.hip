@@ -1092,7 +1092,9 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec_class, int64_t n, doubl
         };
         std::vector<nbody_plan> cand;
         const nbody_plan base = effective_plan(ctx, prec, cls, n);
-        cand.push_back(base);
+        // a spatially ordered plan sums whole systems only, and the sweep
+        // above covers a prefix of the sources when n > nsrc
+        if (base.jsrc < 2 || n <= nsrc) cand.push_back(base);
         const int max_split = prec == P_FP32 ? 1 : 64;
         for (int jsrc = 0; jsrc <= (cls == NB_PLAN_JERK ? 0 : 1); ++jsrc)
             for (int block : {256, 128})
@@ -1111,7 +1113,7 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec_class, int64_t n, doubl
         const bool prof = ctx->prof;
         ctx->prof = false;
         double spent = 0.0, best_rate = -1.0;
-        nbody_plan best = base;
+        nbody_plan best = cand.empty() ? base : cand[0];
         nbody_status result = NB_OK;
         for (size_t c = 0; c < cand.size(); ++c) {
             if (c > 0 && budget_ms > 0 && spent >= budget_ms) break;

@@ -127,7 +127,15 @@ def test_plan_classes(nb, ctx, orc):
     for bad_code, bad in ((jerk, {"R": 2, "block": 256, "split": 1, "jsrc": 1}),
                           (jerk, {"R": 4, "block": 256, "split": 1, "jsrc": 0}),
                           (pot, {"R": 2, "block": 128, "split": 1, "jsrc": 0}),
-                          (nb.NB_FP64 | 0x300, {"R": 1, "block": 256, "split": 1, "jsrc": 0})):
+                          (nb.NB_FP64 | 0x300, {"R": 1, "block": 256, "split": 1, "jsrc": 0}),
+                          # spatially ordered plans: mixed accelerations only, 256 lanes, R 1 or 2
+                          (nb.NB_FP64, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
+                          (nb.NB_FP32, {"R": 1, "block": 256, "split": 1, "jsrc": 2}),
+                          (nb.NB_MIXED, {"R": 4, "block": 256, "split": 1, "jsrc": 3}),
+                          (nb.NB_MIXED, {"R": 1, "block": 128, "split": 1, "jsrc": 2}),
+                          (nb.NB_MIXED, {"R": 1, "block": 256, "split": 1, "jsrc": 4}),
+                          (nb.NB_MIXED | nb.NB_PLAN_POTENTIAL, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
+                          (nb.NB_MIXED | nb.NB_PLAN_JERK, {"R": 1, "block": 256, "split": 1, "jsrc": 2})):
         with pytest.raises(nb.NBodyError) as ei:
             nb.nbody_plan_set(ctx, bad_code, n, bad)
         assert ei.value.status == nb.NB_EINVAL
@@ -136,3 +144,20 @@ def test_plan_classes(nb, ctx, orc):
         assert tuned["block"] == 256 and tuned["R"] in (1, 2)
         assert nb.nbody_plan_get(ctx, code, n) == tuned
         nb.nbody_plan_set(ctx, code, n, None)
+
+
+def test_autotune_with_spatial_plan_pinned(nb, ctx):
+    # a pinned spatially ordered plan sums whole systems only; autotuning its
+    # key still works (above 32768 particles the sweep covers a prefix of the
+    # sources, so the result is a jsrc 0 or 1 plan)
+    for n, plan in ((40000, {"R": 1, "block": 256, "split": 4, "jsrc": 3}),
+                    (3000, {"R": 2, "block": 256, "split": 2, "jsrc": 2})):
+        print(f"[case] autotune n={n} pinned {plan}", flush=True)
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, n, plan)
+        try:
+            tuned = nb.nbody_autotune(ctx, nb.NB_MIXED, n, 50.0)
+            assert nb.nbody_plan_get(ctx, nb.NB_MIXED, n) == tuned
+            if n > 32768:
+                assert tuned["jsrc"] in (0, 1), tuned
+        finally:
+            nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
