@@ -304,7 +304,10 @@ NBODY_API nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, co
  *   NB_PLAN_POTENTIAL  the float64 potential pass of nbody_diag (256 lanes,
  *                      R = 1 or 2, jsrc 0 or 1);
  *   NB_PLAN_JERK       the acceleration-and-jerk sum of the Hermite scheme
- *                      (256 lanes, R = 1 or 2, jsrc 0).
+ *                      (256 lanes, R = 1 or 2, jsrc 0; or jsrc 2 for NB_MIXED:
+ *                      spatial order as for the acceleration, far source tiles
+ *                      with tile-local float32 positions and velocities, whole
+ *                      systems only, jsrc 0 under stream capture).
  * Plans of each class are pinned per precision and size class separately. */
 #define NB_PLAN_ACCEL 0x000
 #define NB_PLAN_POTENTIAL 0x100

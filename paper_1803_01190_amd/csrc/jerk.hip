@@ -18,10 +18,12 @@
 // corrector to the particle's own current state:
 //   v' = v + (a + a1) dt/2 + (j - j1) dt^2/12,
 //   r' = r + (v + v') dt/2 + (a - a1) dt^2/12,   a, j <- a1, j1.
+#include <algorithm>
 #include <type_traits>
 
 #include "nbody_internal.h"
 #include "halo.h"
+#include "jerk_local.h"
 
 namespace nb {
 namespace {
@@ -291,7 +293,212 @@ hipError_t pick(const JerkLaunch &J, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision in spatial order (jerk plans with jsrc = 2).  Targets and
+// sources are the system's particles sorted along a Morton curve, with a
+// bounding box per tile of 256 (order.hip).  For a source tile whose box is
+// farther from the workgroup's targets' box than its own diagonal, positions
+// are taken relative to the tile's centre c and velocities relative to the
+// velocity of the tile's first source w: sources store fl32(x_j - c) and
+// fl32(v_j - w) once per tile, targets form fl32(x_i - c) and fl32(v_i - w)
+// once per tile, and each separation is one float32 subtraction.  The
+// position rounding is at most u (|x_j - c| + |x_i - c|) < 2u r, as for the
+// acceleration; the velocity rounding is at most u (|v_j - w| + |v_i - w|),
+// i.e. u times the relative velocity plus twice the tile's velocity spread.
+// Nearer tiles take the float64-formed separations.
+
+// Far-tile pair term from float32 tile-local coordinates.
+template <int R, bool SAFE>
+__device__ __forceinline__ void interact_far(JLane<P_MIXED, R> &L, const SF &s, const float *rx, const float *ry,
+                                             const float *rz, const float *ru, const float *rv, const float *rw,
+                                             float eps2f) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float dx = s.x - rx[r], dy = s.y - ry[r], dz = s.z - rz[r];
+        const float du = s.u - ru[r], dv = s.v - rv[r], dw = s.w - rw[r];
+        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2f)));
+        float y = __builtin_amdgcn_rsqf(r2);
+        if constexpr (SAFE) y = (r2 >= 1.17549435e-38f) ? y : 0.0f;
+        const float y2 = y * y;
+        const float sm = (s.m * y) * y2;
+        const float rvd = __builtin_fmaf(dx, du, __builtin_fmaf(dy, dv, dz * dw));
+        const float t = (-3.0f * rvd) * y2;
+        L.ax[r] = __builtin_fmaf(sm, dx, L.ax[r]);
+        L.ay[r] = __builtin_fmaf(sm, dy, L.ay[r]);
+        L.az[r] = __builtin_fmaf(sm, dz, L.az[r]);
+        L.jx[r] = __builtin_fmaf(sm, __builtin_fmaf(t, dx, du), L.jx[r]);
+        L.jy[r] = __builtin_fmaf(sm, __builtin_fmaf(t, dy, dv), L.jy[r]);
+        L.jz[r] = __builtin_fmaf(sm, __builtin_fmaf(t, dz, dw), L.jz[r]);
+    }
+}
+
+// Velocities in the spatial order.
+__global__ __launch_bounds__(256) void k_gather_vel(const double *vx, const double *vy, const double *vz,
+                                                    const int32_t *perm, int64_t n, double *pu, double *pv,
+                                                    double *pw) {
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        const int64_t i = perm[q];
+        pu[q] = vx[i]; pv[q] = vy[i]; pw[q] = vz[i];
+    }
+}
+
+// Sorted system: positions, masses and boxes from the order, velocities pu..pw.
+struct JOrd {
+    const int32_t *perm;
+    const double *px, *py, *pz, *pm, *pu, *pv, *pw;
+    const double *tbox;
+};
+
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_jerk_local(JerkLaunch J, JOrd O, int64_t chunk) {
+    constexpr int BLOCK = 256;
+    __shared__ SF ftile[BLOCK];
+    __shared__ SX dtile[BLOCK];
+    const int64_t n = J.sc.n;
+    const int64_t ib = (int64_t)blockIdx.x * (BLOCK * R);  // sorted positions
+    const int64_t jb = (int64_t)blockIdx.y * chunk;
+    const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+    const int t = threadIdx.x;
+    JLane<P_MIXED, R> L;
+    L.km15 = -1.5;
+    L.km3 = -3.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = ib + (int64_t)r * BLOCK + t;
+        const bool ok = q < n;
+        L.x[r] = ok ? O.px[q] : 0.0; L.y[r] = ok ? O.py[q] : 0.0; L.z[r] = ok ? O.pz[q] : 0.0;
+        L.u[r] = ok ? O.pu[q] : 0.0; L.v[r] = ok ? O.pv[q] : 0.0; L.w[r] = ok ? O.pw[q] : 0.0;
+        L.ax[r] = L.ay[r] = L.az[r] = L.jx[r] = L.jy[r] = L.jz[r] = 0.0f;
+        L.oax[r] = L.oay[r] = L.oaz[r] = L.ojx[r] = L.ojy[r] = L.ojz[r] = 0.0;
+    }
+    // box of this workgroup's targets: the boxes of its R tiles
+    const int64_t ntile = (n + BLOCK - 1) / BLOCK;
+    double bmin[3] = {1.0e308, 1.0e308, 1.0e308}, bmax[3] = {-1.0e308, -1.0e308, -1.0e308};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t tt = ib / BLOCK + r;
+        if (tt < ntile) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bmin[c] = fmin(bmin[c], O.tbox[6 * tt + c]);
+                bmax[c] = fmax(bmax[c], O.tbox[6 * tt + 3 + c]);
+            }
+        }
+    }
+    for (int64_t jt = jb; jt < je; jt += BLOCK) {
+        const double *tb = O.tbox + 6 * (jt / BLOCK);
+        double gap2 = 0.0, diag2 = 0.0, ctr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double lo = tb[c], hi = tb[3 + c];
+            const double g = fmax(0.0, fmax(lo - bmax[c], bmin[c] - hi));
+            gap2 += g * g;
+            diag2 += (hi - lo) * (hi - lo);
+            ctr[c] = 0.5 * (lo + hi);
+        }
+        const int64_t j = jt + t;
+        const bool ok = j < je;
+        if (gap2 > diag2) {  // far tile (a uniform branch)
+            const double wu = O.pu[jt], wv = O.pv[jt], ww = O.pw[jt];
+            SF e;
+            e.x = ok ? (float)(O.px[j] - ctr[0]) : 0.0f;
+            e.y = ok ? (float)(O.py[j] - ctr[1]) : 0.0f;
+            e.z = ok ? (float)(O.pz[j] - ctr[2]) : 0.0f;
+            e.u = ok ? (float)(O.pu[j] - wu) : 0.0f;
+            e.v = ok ? (float)(O.pv[j] - wv) : 0.0f;
+            e.w = ok ? (float)(O.pw[j] - ww) : 0.0f;
+            e.m = ok ? (float)O.pm[j] : 0.0f;
+            e.pad = 0.0f;
+            ftile[t] = e;
+            float rx[R], ry[R], rz[R], ru[R], rv[R], rw[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                rx[r] = (float)(L.x[r] - ctr[0]); ry[r] = (float)(L.y[r] - ctr[1]); rz[r] = (float)(L.z[r] - ctr[2]);
+                ru[r] = (float)(L.u[r] - wu); rv[r] = (float)(L.v[r] - wv); rw[r] = (float)(L.w[r] - ww);
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int k = 0; k < BLOCK; ++k) interact_far<R, SAFE>(L, ftile[k], rx, ry, rz, ru, rv, rw, J.sc.eps2f);
+        } else {
+            SX e;
+            e.x = ok ? O.px[j] : 0.0; e.y = ok ? O.py[j] : 0.0; e.z = ok ? O.pz[j] : 0.0;
+            e.u = ok ? O.pu[j] : 0.0; e.v = ok ? O.pv[j] : 0.0; e.w = ok ? O.pw[j] : 0.0;
+            e.m = ok ? (float)O.pm[j] : 0.0f;
+            e.pad = 0.0f;
+            dtile[t] = e;
+            __syncthreads();
+#pragma unroll 2
+            for (int k = 0; k < BLOCK; ++k) interact<P_MIXED, R, SAFE>(L, dtile[k], J.sc.eps2, J.sc.eps2f);
+        }
+        flush(L);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = ib + (int64_t)r * BLOCK + t;
+        if (q >= n) continue;
+        double o[6];
+        raw<P_MIXED, R>(L, r, o);
+        if (J.split > 1) {
+            double *p = J.part + (int64_t)blockIdx.y * 6 * n + q;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) p[c * n] = o[c];
+        } else {
+            finish<P_MIXED>(J, O.perm[q], o);
+        }
+    }
+}
+
+// Fixed-order reduction of the split partial sums (rows in the spatial
+// order), then the epilogue of each row's particle.
+__global__ __launch_bounds__(256) void k_pair_jerk_local_reduce(JerkLaunch J, const int32_t *perm) {
+    const int64_t n = J.sc.n;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < J.split; ++s) {
+        const double *b = J.part + (int64_t)s * 6 * n + q;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] += b[c * n];
+    }
+    finish<P_MIXED>(J, perm[q], o);
+}
+
+template <int R>
+hipError_t go_local(const JerkLaunch &J, const JOrd &O, hipStream_t s) {
+    const int64_t n = J.sc.n;
+    const int64_t per = 256LL * R;
+    const int64_t nbx = (n + per - 1) / per;
+    const int64_t per_chunk = (n + J.split - 1) / J.split;
+    const int64_t chunk = ((per_chunk + 255) / 256) * 256;
+    dim3 grid((unsigned)nbx, (unsigned)J.split);
+    if (J.sc.safe32)
+        hipLaunchKernelGGL((k_pair_jerk_local<R, true>), grid, dim3(256), 0, s, J, O, chunk);
+    else
+        hipLaunchKernelGGL((k_pair_jerk_local<R, false>), grid, dim3(256), 0, s, J, O, chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || J.split <= 1) return e;
+    hipLaunchKernelGGL(k_pair_jerk_local_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, J, O.perm);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_pair_jerk_local(const JerkLaunch &J, const LocalOrder &lo, double *vel, hipStream_t s) {
+    const int64_t n = J.sc.n;
+    if (J.sc.prec != P_MIXED || J.block != 256 || J.split < 1 || J.i0 != 0 || J.i1 != n || !lo.perm || !vel)
+        return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    double *pu = vel, *pv = vel + n, *pw = vel + 2 * n;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_gather_vel, dim3(g), dim3(256), 0, s, J.vx, J.vy, J.vz, lo.perm, n, pu, pv, pw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const JOrd O{lo.perm, lo.px, lo.py, lo.pz, lo.pm, pu, pv, pw, lo.tbox};
+    if (J.R == 1) return go_local<1>(J, O, s);
+    if (J.R == 2) return go_local<2>(J, O, s);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_pair_jerk(const JerkLaunch &J, hipStream_t s) {
     if (J.block != 256 || J.split < 1) return hipErrorInvalidValue;

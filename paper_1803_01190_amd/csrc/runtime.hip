@@ -25,6 +25,7 @@
 
 #include "nbody.h"
 #include "nbody_internal.h"
+#include "jerk_local.h"
 
 using namespace nb;
 
@@ -41,6 +42,8 @@ struct nbody_ctx {
     size_t integ_cap = 0;     // doubles
     double *order = nullptr;  // spatial order of a system (jsrc 2 and 3 plans)
     size_t order_cap = 0;     // doubles
+    double *jvel = nullptr;   // velocities in that order (jerk plans with jsrc 2)
+    size_t jvel_cap = 0;      // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
     // Scratch outgrown by a larger call is kept (not freed) until the
     // context is destroyed: a HIP graph captured earlier may still use it,
@@ -431,8 +434,10 @@ nbody_plan jerk_plan(const nbody_ctx *ctx, int prec, int64_t n) {
     return p;
 }
 
+// jsrc 0: LDS source tiles; jsrc 2 (mixed): spatial order, whole systems only.
 bool jerk_plan_supported(int prec, const nbody_plan &p) {
-    return p.block == 256 && (p.R == 1 || p.R == 2) && p.jsrc == 0 && (prec != P_FP32 || p.split == 1);
+    return p.block == 256 && (p.R == 1 || p.R == 2) && (p.jsrc == 0 || (p.jsrc == 2 && prec == P_MIXED)) &&
+           (prec != P_FP32 || p.split == 1);
 }
 
 nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, const nbody_plan &pl, hipStream_t s) {
@@ -441,6 +446,20 @@ nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, const nbody_plan &pl, hipSt
     if (!jerk_plan_supported(J.sc.prec, pl))
         return fail(ctx, NB_ENOTSUP, "unsupported jerk plan R=%d block=%d split=%d jsrc=%d", pl.R, pl.block,
                     pl.split, pl.jsrc);
+    if (pl.jsrc == 2) {
+        if (J.i0 != 0 || J.i1 != J.sc.n)
+            return fail(ctx, NB_ENOTSUP, "a spatially ordered jerk plan (jsrc 2) sums whole systems only");
+        if (capturing(s)) {
+            // the ordering uses a library sort; under stream capture the
+            // plan runs with LDS source tiles in the particles' own order
+            nbody_plan p0 = pl;
+            p0.jsrc = 0;
+            return run_jerk(ctx, J, p0, s);
+        }
+        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(J.sc.n) + 7) / 8);
+        if (r == NB_OK) r = ensure(ctx, &ctx->jvel, &ctx->jvel_cap, 3 * (size_t)J.sc.n);
+        if (r != NB_OK) return r;
+    }
     J.R = pl.R;
     J.block = pl.block;
     J.split = pl.split;
@@ -450,6 +469,19 @@ nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, const nbody_plan &pl, hipSt
         J.part = ctx->part;
     }
     Timed t(ctx, s, 0, rows * J.sc.n);
+    if (pl.jsrc == 2) {
+        State st{};
+        st.x = const_cast<double *>(J.x);
+        st.y = const_cast<double *>(J.y);
+        st.z = const_cast<double *>(J.z);
+        st.m = J.m;
+        LocalOrder lo{};
+        hipError_t e = launch_local_order(st, J.sc.n, ctx->order, &lo, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "spatial order");
+        e = launch_pair_jerk_local(J, lo, ctx->jvel, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "acceleration-and-jerk launch");
+        return NB_OK;
+    }
     const hipError_t e = launch_pair_jerk(J, s);
     if (e != hipSuccess) return hipfail(ctx, e, "acceleration-and-jerk launch");
     return NB_OK;
@@ -503,6 +535,7 @@ nbody_status nbody_ctx_destroy(nbody_ctx *ctx) {
     if (ctx->phi) (void)hipFree(ctx->phi);
     if (ctx->integ) (void)hipFree(ctx->integ);
     if (ctx->order) (void)hipFree(ctx->order);
+    if (ctx->jvel) (void)hipFree(ctx->jvel);
     for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->sysc) (void)hipFree(ctx->sysc);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -1008,7 +1041,8 @@ static nbody_plan effective_plan(nbody_ctx *ctx, int prec, int cls, int64_t n) {
 
 static bool class_plan_supported(int prec, int cls, const nbody_plan &p) {
     if (p.split < 1 || p.split > 1024) return false;
-    if (cls == NB_PLAN_JERK) return p.block == 256 && (p.R == 1 || p.R == 2) && p.jsrc == 0;
+    if (cls == NB_PLAN_JERK)
+        return p.block == 256 && (p.R == 1 || p.R == 2) && (p.jsrc == 0 || (p.jsrc == 2 && prec == P_MIXED));
     return pair_config_supported(prec, p.R, p.block, p.jsrc, cls == NB_PLAN_POTENTIAL ? MODE_PHI : MODE_ACC);
 }
 

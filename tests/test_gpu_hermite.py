@@ -193,3 +193,89 @@ def test_hermite_zero_steps_and_empty(nb, ctx):
     after = s.numpy()
     for k in before:
         assert np.array_equal(before[k], after[k])
+
+
+# mixed jerk plans in spatial order (jsrc 2): far source tiles with tile-local
+# float32 positions and velocities; the same gate as the other mixed plans
+JERK_LOCAL = [dict(R=R, block=256, split=s, jsrc=2) for R in (1, 2) for s in (1, 3)]
+
+
+def _aj_with_plan(nb, ctx, ic, prm, plan):
+    code = nb.NB_MIXED | nb.NB_PLAN_JERK
+    nb.nbody_plan_set(ctx, code, ic["x"].size, plan)
+    try:
+        return gpu_aj(nb, ctx, ic, prm)
+    finally:
+        nb.nbody_plan_set(ctx, code, ic["x"].size, None)
+
+
+@pytest.mark.parametrize("plan", JERK_LOCAL, ids=lambda p: f"R{p['R']}s{p['split']}")
+@pytest.mark.parametrize("model,n", [("plummer", 4099), ("disk", 20000), ("plummer", 300)])
+def test_accel_jerk_spatial_order(nb, ctx, orc, plan, model, n):
+    print(f"[case] accel_jerk mixed spatial order {model} n={n} plan={plan}", flush=True)
+    if model == "disk":
+        h = wl.default_halo()
+        ic, eps = wl.exp_disk(n, 208), 0.02
+        prm = nb.Params(eps=eps, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+        halo = orc.Halo(h.v2, h.rc)
+    else:
+        ic, eps, halo = wl.plummer(n, 209), 0.01, None
+        prm = nb.Params(eps=eps, prec=nb.NB_MIXED)
+    a, j = _aj_with_plan(nb, ctx, ic, prm, plan)
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(ic, 1.0, eps, halo, want_scale=True)
+    if halo is not None:
+        # the halo terms join the scale: the halo's own a and j magnitudes
+        hx, hy, hz = orc.halo_accel(ic["x"], ic["y"], ic["z"], halo)
+        A = A + np.sqrt(hx ** 2 + hy ** 2 + hz ** 2)
+        _, _, _, hjx, hjy, hjz = orc.accel_jerk({**ic, "m": np.zeros(n)}, 1.0, eps, halo)
+        J = J + np.sqrt(hjx ** 2 + hjy ** 2 + hjz ** 2)
+    assert cond_err(a, (ax, ay, az), A) <= TOL["mixed"]
+    assert cond_err(j, (jx, jy, jz), J) <= TOL["mixed"]
+    # and close to the plan that forms every separation in float64
+    a0, j0 = _aj_with_plan(nb, ctx, ic, prm, dict(R=2, block=256, split=1, jsrc=0))
+    assert cond_err(a, a0, A) <= TOL["mixed"] and cond_err(j, j0, J) <= TOL["mixed"]
+
+
+@pytest.mark.parametrize("split", [1, 4])
+def test_hermite_spatial_order_steps(nb, ctx, split):
+    # Hermite steps under the spatially ordered jerk plan (corrector in the
+    # pair kernel with split 1, in the reduction otherwise): deterministic,
+    # and within the mixed force error of the steps under the jsrc 0 plan
+    print(f"[case] hermite mixed spatial order split={split}", flush=True)
+    n, steps, dt = 20000, 5, 1e-3
+    ic = wl.exp_disk(n, 210)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    code = nb.NB_MIXED | nb.NB_PLAN_JERK
+    local = {"R": 2, "block": 256, "split": split, "jsrc": 2}
+    outs = []
+    for plan in (local, local, {"R": 2, "block": 256, "split": 1, "jsrc": 0}):
+        nb.nbody_plan_set(ctx, code, n, plan)
+        try:
+            outs.append(run_steps(nb, ctx, ic, prm, "hermite", dt, steps))
+        finally:
+            nb.nbody_plan_set(ctx, code, n, None)
+    for k in ("x", "vx", "ax", "jx"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.max(np.abs(outs[0][k] - outs[2][k])) <= 1e-9 * np.max(np.abs(outs[2][k])), k
+
+
+def test_jerk_spatial_order_edges(nb, ctx, orc):
+    # eps = 0 with a coincident pair (self and coincident pairs drop out), and
+    # a translated, boosted system (tile-local coordinates keep the accuracy)
+    print("[case] jerk spatial order edges", flush=True)
+    plan = dict(R=2, block=256, split=2, jsrc=2)
+    ic = wl.plummer(3000, 211)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        ic[k][5] = ic[k][6]
+    a, j = _aj_with_plan(nb, ctx, ic, nb.Params(eps=0.0, prec=nb.NB_MIXED), plan)
+    assert np.all(np.isfinite(np.concatenate([*a, *j])))
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(ic, 1.0, 0.0, want_scale=True)
+    assert cond_err(a, (ax, ay, az), A) <= TOL["mixed"] and cond_err(j, (jx, jy, jz), J) <= TOL["mixed"]
+    sh = dict(ic)
+    sh["x"] = ic["x"] + 1000.0
+    sh["vy"] = ic["vy"] + 50.0
+    a2, j2 = _aj_with_plan(nb, ctx, sh, nb.Params(eps=0.01, prec=nb.NB_MIXED), plan)
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(ic, 1.0, 0.01, want_scale=True)
+    assert cond_err(a2, (ax, ay, az), A) <= TOL["mixed"] and cond_err(j2, (jx, jy, jz), J) <= TOL["mixed"]

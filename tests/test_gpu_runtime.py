@@ -135,7 +135,8 @@ def test_plan_classes(nb, ctx, orc):
                           (nb.NB_MIXED, {"R": 1, "block": 128, "split": 1, "jsrc": 2}),
                           (nb.NB_MIXED, {"R": 1, "block": 256, "split": 1, "jsrc": 4}),
                           (nb.NB_MIXED | nb.NB_PLAN_POTENTIAL, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
-                          (nb.NB_MIXED | nb.NB_PLAN_JERK, {"R": 1, "block": 256, "split": 1, "jsrc": 2})):
+                          (nb.NB_MIXED | nb.NB_PLAN_JERK, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
+                          (nb.NB_FP64 | nb.NB_PLAN_JERK, {"R": 1, "block": 256, "split": 1, "jsrc": 2})):
         with pytest.raises(nb.NBodyError) as ei:
             nb.nbody_plan_set(ctx, bad_code, n, bad)
         assert ei.value.status == nb.NB_EINVAL

@@ -6,7 +6,8 @@ NB_PLAN_* classes in include/nbody.h:
     float32); jsrc 0 or 1, or 2 / 3 (spatial order) for mixed with 256 lanes
     and R 1 or 2;
   * potential pass: 256 lanes, R 1 or 2, jsrc 0 or 1;
-  * acceleration-and-jerk sum: 256 lanes, R 1 or 2, jsrc 0.
+  * acceleration-and-jerk sum: 256 lanes, R 1 or 2, jsrc 0, or 2 (spatial
+    order) for mixed.
 A bad entry would make load_plans fail on the GPU; this checks the file on
 the host.  Keys are ceil(log2 n) of the size class."""
 import json
@@ -21,7 +22,7 @@ def _ok(prec: str, cls: str, p: dict) -> bool:
     if not (isinstance(split, int) and 1 <= split <= 1024):
         return False
     if cls == "jerk":
-        return block == 256 and R in (1, 2) and jsrc == 0
+        return block == 256 and R in (1, 2) and (jsrc == 0 or (jsrc == 2 and prec == "mixed"))
     if cls == "potential":
         return block == 256 and R in (1, 2) and jsrc in (0, 1)
     if jsrc in (2, 3):
@@ -71,6 +72,8 @@ def test_plan_rule_rejects_known_bad_plans():
         ("fp64", "potential", dict(good, jsrc=2)),
         ("fp64", "potential", dict(good, block=128)),
         ("fp64", "jerk", dict(good, jsrc=1)),
+        ("fp64", "jerk", dict(good, jsrc=2)),
+        ("mixed", "jerk", dict(good, jsrc=3)),
         ("fp64", "jerk", dict(good, R=4)),
         ("fp64", "accel", dict(good, split=0)),
     ]
