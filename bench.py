@@ -593,6 +593,7 @@ def bench_hermite(args):
             "value": args.steps * inter / wall, "ms_per_step": 1e3 * wall / args.steps,
             "latency_ms": {"p50": percentile(step_ms, 0.5), "p99": percentile(step_ms, 0.99)},
             "pair_kernel_ms": pair_ms, "pair_launches": prof["accel_launches"],
+            "plan": nb.nbody_plan_get(ctx.h, nb.PREC[prec] | nb.NB_PLAN_JERK, n),
             "update_ms_per_step": prof["update_ms"] / max(args.steps, 1), "achieved_tflops": tflops,
             "drift": {"dE_rel": abs(d1["E"] - d0["E"]) / abs(d0["E"]),
                       "dLz_rel": abs(d1["Lz"] - d0["Lz"]) / abs(d0["Lz"]), "steps": args.steps},
@@ -632,7 +633,9 @@ def bench_hermite(args):
         "latency_ms": r0["latency_ms"],
         "roofline": {"bound": "alu", "achieved": r0["achieved_tflops"], "peak": PEAK_TFLOPS[head],
                      "unit": "TFLOP/s", "frac": r0["achieved_tflops"] / PEAK_TFLOPS[head], "traffic": None,
-                     "kernel": "acceleration and jerk (k_pair_jerk)",
+                     "kernel": ("acceleration and jerk in spatial order (k_pair_jerk_local, with its "
+                                "ordering kernels)" if r0["plan"].get("jsrc") == 2 else
+                                "acceleration and jerk (k_pair_jerk)"),
                      "flops_per_interaction": JERK_FLOPS_PER_INTERACTION, "interactions_per_launch": inter},
         "cpu_baseline": cpu, "errors": errs or None,
         "per_precision": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
