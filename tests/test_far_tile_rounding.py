@@ -1,0 +1,141 @@
+"""Rounding of the mixed-precision far-tile forms, checked on the host.
+
+The spatially ordered mixed plans take a source tile as "far" from a group of
+targets when the gap between their bounding boxes exceeds the tile's own
+diagonal; for such tiles the pair separations come from float32 coordinates
+relative to the tile's centre c, either subtracted per pair (x_j' - x_i') or
+through the expanded squared distance q_j + q_i - 2 x_i'.x_j' with the force
+sum taken as sum s_j x_j' - x_i' sum s_j.  The stated bound for the mixed
+path is about 10u per pair plus 255u of the tile's sum of |f| (u = 2^-24).
+
+This emulates both forms with numpy float32 arithmetic (a fused multiply-add
+as an exact float64 product and sum rounded once to float32; the reciprocal
+square root correctly rounded) and checks them against a float64 sum of the
+softened pair terms of Eqs. (1)-(2), for tiles of random shape and size,
+targets at gaps just above the criterion and far beyond it, translated
+systems and zero softening (measured worst case: about 12u for either form).
+It also shows the criterion is needed: for targets next to the tile both
+forms lose the bound."""
+import numpy as np
+import pytest
+
+U = 2.0 ** -24
+T = 256
+
+
+def f32(v):
+    return np.asarray(v, dtype=np.float64).astype(np.float32)
+
+
+def fma32(a, b, c):
+    # exact float32 x float32 product in float64, one rounding of the sum
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
+def rsq32(r2):
+    return (1.0 / np.sqrt(r2.astype(np.float64))).astype(np.float32)
+
+
+def exact(xs, m, xt, eps2):
+    d = xs[None, :, :] - xt[:, None, :]                       # targets x sources x 3
+    r2 = (d * d).sum(-1) + eps2
+    w = np.where(r2 > 0, m[None, :] / np.where(r2 > 0, r2, 1.0) ** 1.5, 0.0)
+    f = (w[:, :, None] * d).sum(1)
+    scale = (w * np.sqrt((d * d).sum(-1))).sum(1)             # sum of |f_j|
+    return f, scale
+
+
+def subtracted(xs, m, xt, eps2, c):
+    sj = f32(xs - c)
+    ti = f32(xt - c)
+    e2 = np.float32(eps2)
+    acc = np.zeros((xt.shape[0], 3), np.float32)
+    for j in range(xs.shape[0]):
+        d = sj[j][None, :] - ti                               # float32 subtraction
+        r2 = fma32(d[:, 0], d[:, 0], fma32(d[:, 1], d[:, 1], fma32(d[:, 2], d[:, 2], np.full(len(d), e2))))
+        y = np.where(r2 > 0, rsq32(np.where(r2 > 0, r2, 1)), np.float32(0))
+        sc = (np.float32(m[j]) * y) * (y * y)
+        for k in range(3):
+            acc[:, k] = fma32(sc, d[:, k], acc[:, k])
+    return acc.astype(np.float64)
+
+
+def expanded(xs, m, xt, eps2, c):
+    sj = f32(xs - c)
+    qj = f32(((xs - c) ** 2).sum(1))
+    dti = xt - c
+    w = f32(-2.0 * dti)
+    qi = f32((dti ** 2).sum(1) + eps2)
+    acc = np.zeros((xt.shape[0], 3), np.float32)
+    ssum = np.zeros(xt.shape[0], np.float32)
+    for j in range(xs.shape[0]):
+        base = (np.float32(qj[j]) + qi).astype(np.float32)
+        r2 = fma32(np.full(len(w), sj[j, 0]), w[:, 0],
+                   fma32(np.full(len(w), sj[j, 1]), w[:, 1], fma32(np.full(len(w), sj[j, 2]), w[:, 2], base)))
+        y = np.where(r2 > 0, rsq32(np.where(r2 > 0, r2, 1)), np.float32(0))
+        sc = (np.float32(m[j]) * y) * (y * y)
+        for k in range(3):
+            acc[:, k] = fma32(sc, np.full(len(sc), sj[j, k]), acc[:, k])
+        ssum = (ssum + sc).astype(np.float32)
+    # the x_i' sum term in float64, once per tile
+    return acc.astype(np.float64) - dti * ssum.astype(np.float64)[:, None]
+
+
+def tile_and_targets(rng, gap_over_diag, shift, flat):
+    ext = np.array([1.0, rng.uniform(0.2, 1.0), 0.05 if flat else rng.uniform(0.2, 1.0)])
+    ext = ext * 10.0 ** rng.uniform(-2, 1)
+    xs = shift + rng.uniform(-0.5, 0.5, (T, 3)) * ext
+    lo, hi = xs.min(0), xs.max(0)
+    c = 0.5 * (lo + hi)
+    diag = np.linalg.norm(hi - lo)
+    # targets on random directions at a given gap from the tile's box
+    u = rng.normal(size=(48, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    half = 0.5 * (hi - lo)
+    reach = np.abs(u) @ half                                  # box support along u
+    xt = c + u * (reach + gap_over_diag * diag)[:, None]
+    m = rng.uniform(0.5, 1.5, T) / T
+    return xs, m, xt, c, diag
+
+
+@pytest.mark.parametrize("form", ["subtracted", "expanded"])
+@pytest.mark.parametrize("gap_over_diag", [1.05, 2.0, 30.0])
+@pytest.mark.parametrize("shift", [0.0, 1.0e3])
+def test_far_tile_forms_within_mixed_bound(form, gap_over_diag, shift):
+    rng = np.random.default_rng(int(gap_over_diag * 100) + int(shift) + (form == "expanded"))
+    fn = subtracted if form == "subtracted" else expanded
+    worst = 0.0
+    for trial in range(4):
+        xs, m, xt, c, diag = tile_and_targets(rng, gap_over_diag, shift, flat=trial % 2 == 0)
+        # keep only targets outside the tile's box by more than its diagonal
+        lo, hi = xs.min(0), xs.max(0)
+        g = np.maximum(0.0, np.maximum(lo - xt, xt - hi))
+        far = (g * g).sum(1) > diag * diag
+        xt = xt[far]
+        if xt.size == 0:
+            continue
+        for eps2 in (0.0, (0.05 * diag) ** 2):
+            f, scale = exact(xs, m, xt, eps2)
+            got = fn(xs, m, xt, eps2, c)
+            err = np.linalg.norm(got - f, axis=1) / scale
+            worst = max(worst, float(err.max()))
+    assert worst <= (10 + 255) * U, worst
+    # and in practice far below the worst case
+    assert worst <= 40 * U, worst
+
+
+def test_expanded_form_needs_the_far_criterion():
+    # targets next to (here among) the tile's sources: the tile-local
+    # coordinates are no longer small against the separations, both forms
+    # lose the bound (the expanded one by far more, its squared distance
+    # cancels), so such tiles take float64-formed separations
+    rng = np.random.default_rng(3)
+    xs = rng.uniform(-0.5, 0.5, (T, 3))
+    m = np.full(T, 1.0 / T)
+    c = 0.5 * (xs.min(0) + xs.max(0))
+    xt = xs[:8] + 1e-4 * rng.normal(size=(8, 3))             # targets among the sources
+    f, scale = exact(xs, m, xt, 0.0)
+    err_exp = (np.linalg.norm(expanded(xs, m, xt, 0.0, c) - f, axis=1) / scale).max()
+    err_sub = (np.linalg.norm(subtracted(xs, m, xt, 0.0, c) - f, axis=1) / scale).max()
+    assert err_sub > (10 + 255) * U, err_sub
+    assert err_exp > 100 * err_sub, (err_exp, err_sub)
