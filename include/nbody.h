@@ -180,7 +180,10 @@ NBODY_API nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const n
 /* Same as nbody_accel for the targets i in [i0, i1) only (all n particles
  * are sources).  Rows [i0, i1) are bitwise equal to those of nbody_accel
  * under the same plan; the other rows are untouched.  This is one GPU's
- * share when the targets of one system are split across several GPUs. */
+ * share when the targets of one system are split across several GPUs.
+ * A spatially ordered plan (jsrc 2 or 3) sums whole systems only: a proper
+ * subrange under such a plan returns NB_ENOTSUP (pin a jsrc 0 or 1 plan for
+ * the size class to use row ranges). */
 NBODY_API nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                               int64_t i0, int64_t i1, void *stream);
 
