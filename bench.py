@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--long-steps", type=int, default=10000, help="longrun: steps per run")
     ap.add_argument("--long-runs", default="fp64,fp64_alt,mixed,fp32",
                     help="longrun: runs (fp64_alt: float64 with another summation order)")
-    ap.add_argument("--out-dir", default="gpurun_out/longrun", help="longrun: series and maps")
+    ap.add_argument("--out-dir", default="longrun_out", help="longrun: series and maps")
     ap.add_argument("--stop-at", type=int, default=None,
                     help="longrun: stop each run at this step and save it for --resume-dir")
     ap.add_argument("--resume-dir", default=None, help="longrun: continue the runs saved there")

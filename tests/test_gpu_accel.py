@@ -2,7 +2,8 @@
 
 Float64 gate: eps_rms <= 1e-12 and eps_cond <= 1e-12 at every size and
 launch plan (see oracle.metrics for the definitions).  Mixed and float32
-gates are derived in the design doc from the arithmetic of those paths.
+gates follow from the arithmetic of those paths (the bounds are stated with
+the tolerances below).
 """
 import numpy as np
 import pytest
