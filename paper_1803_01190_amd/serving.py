@@ -69,21 +69,8 @@ class Backend:
         raise NotImplementedError
 
     def finish(self, handle) -> Result:
-        nb, torch = self.nb, self.torch
-        e = self.live[handle]
-        req, s, prm = e["req"], e["sys"], e["prm"]
-        d = state = None
-        with torch.cuda.stream(self.stream):
-            dt = nb.nbody_diag(self.ctx, s, prm, stream=self.stream) if self.diagnostics else None
-            if self.diagnostics or self.keep_state:
-                self.stream.synchronize()
-                d = nb.diag_dict(dt) if dt is not None else None
-                state = s.numpy() if self.keep_state else None
-        res = Result(req.id, req.n, req.steps, "fp64" if req.fp64 else "mixed", req.t_arrive, state=state, diag=d)
-        if d is not None and not all(math.isfinite(v) for v in d.values()):
-            res.error = "non-finite state"
-        self._release(handle)
-        return res
+        """Result of a request that has run all its steps; releases it."""
+        raise NotImplementedError
 
     def drop(self, handle) -> None:  # free without a result (after a failure)
         raise NotImplementedError

@@ -70,6 +70,46 @@ def test_disk_2p20_sampled(nb, ctx, orc, disk20, prec):
         assert net <= 1e-13 * scale, (net, scale)
 
 
+# acceleration and jerk of the fourth-order Hermite scheme in the launch
+# configuration the Hermite benchmark times (the tuned jerk plans: for mixed,
+# the spatially ordered plan with R 1 and a 32-way split from N = 2^17 on)
+JERK_GATE = {"fp64": (1e-12, 1e-12), "mixed": (2e-7, 5e-7), "fp32": (2e-3, 2e-3)}
+
+
+@pytest.mark.parametrize("log2n", [17, 20])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_disk_jerk_sampled(nb, ctx, orc, disk20, prec, log2n):
+    n = 1 << log2n
+    print(f"[case] disk 2^{log2n} {prec} acceleration and jerk, sampled rows", flush=True)
+    ic = disk20 if log2n == 20 else wl.exp_disk(n, 2)
+    h = wl.default_halo()
+    nb.load_plans(ctx)
+    plan = nb.nbody_plan_get(ctx, nb.PREC[prec] | nb.NB_PLAN_JERK, n)
+    if prec == "mixed":
+        assert plan["jsrc"] == 2, plan  # the tuned plan is the one under test
+    prm = nb.Params(eps=0.02, prec=nb.PREC[prec], halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    s = nb.System.from_arrays(ic)
+    nb.nbody_accel_jerk(ctx, s, prm)
+    rng = np.random.default_rng(12)
+    rows = np.sort(rng.choice(n, size=512, replace=False))
+    rt = torch.as_tensor(rows, device="cuda")
+    got = torch.stack([s[k][rt] for k in ("ax", "ay", "az", "jx", "jy", "jz")]).cpu().numpy()
+    halo = orc.Halo(h.v2, h.rc)
+    ax, ay, az, jx, jy, jz, A, J = orc.accel_jerk(ic, 1.0, 0.02, halo, want_scale=True, rows=rows)
+    # the halo's own a and j magnitudes join the scales
+    sub = {k: ic[k][rows] for k in ("x", "y", "z", "vx", "vy", "vz")}
+    _, _, _, hjx, hjy, hjz = orc.accel_jerk({**sub, "m": np.zeros(rows.size)}, 1.0, 0.02, halo)
+    hx, hy, hz = orc.halo_accel(sub["x"], sub["y"], sub["z"], halo)
+    A = A + np.sqrt(hx * hx + hy * hy + hz * hz)
+    J = J + np.sqrt(hjx * hjx + hjy * hjy + hjz * hjz)
+    ea = force_errors(got[:3], np.stack([ax, ay, az]), A)
+    ej = force_errors(got[3:], np.stack([jx, jy, jz]), J)
+    print(f"[err] 2^{log2n} {prec} plan {plan}: a {ea}  j {ej}", flush=True)
+    ga, gj = JERK_GATE[prec]
+    assert ea["eps_cond"] <= ga and ea["eps_rms"] <= ga, ea
+    assert ej["eps_cond"] <= gj, ej
+
+
 @pytest.mark.parametrize("scheme", ["kdk", "o4"])
 def test_disk_2p17_integrators_conserve(nb, ctx, scheme):
     # N = 2^17 disk: second- vs fourth-order.  L_z is conserved by both

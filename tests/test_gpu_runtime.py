@@ -36,6 +36,32 @@ def test_checkpoint_resume_bitwise(nb, ctx, tmp_path, prec):
         assert torch.equal(a[k], c[k]), k
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_checkpoint_resume_hermite_bitwise(nb, ctx, tmp_path, prec):
+    # the Hermite scheme carries a and j of the last predicted state: a
+    # snapshot holds the jerks too, and the resumed run continues bit for bit
+    from paper_1803_01190_amd import checkpoint
+    print(f"[case] hermite resume {prec}", flush=True)
+    ic = wl.exp_disk(3000, 33)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.PREC[prec], halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    a = nb.System.from_arrays(ic)
+    nb.nbody_accel_jerk(ctx, a, prm)
+    nb.nbody_step_hermite(ctx, a, prm, 1e-3, 10)
+    b = nb.System.from_arrays(ic)
+    nb.nbody_accel_jerk(ctx, b, prm)
+    nb.nbody_step_hermite(ctx, b, prm, 1e-3, 4)
+    path = str(tmp_path / "snap_h.npz")
+    checkpoint.save(path, b, prm, t=4e-3, step=4)
+    del b
+    c, prm2, t, step, _ = checkpoint.load(path)
+    assert step == 4 and prm2 == prm
+    nb.nbody_step_hermite(ctx, c, prm2, 1e-3, 6)
+    torch.cuda.synchronize()
+    for k in K + ("jx", "jy", "jz"):
+        assert torch.equal(a[k], c[k]), k
+
+
 @pytest.mark.parametrize("scheme", ["kdk", "o4"])
 def test_single_system_graph_capture(nb, ctx, scheme):
     ic = wl.plummer(5000, 32)

@@ -60,3 +60,29 @@ def test_pins_catch_planted_mistake(tmp_path, name, orig, bad):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"
+
+
+METRICS_SRC = os.path.join(ROOT, "oracle", "metrics.py")
+
+# planted mistakes in the force-error metrics (oracle/metrics.py)
+METRICS_MUTATIONS = [
+    ("conditioned error: mean for max", "\"eps_cond\": float(np.max(d[A > 0] / A[A > 0]))",
+     "\"eps_cond\": float(np.mean(d[A > 0] / A[A > 0]))"),
+    ("difference norm over the wrong axis", "d = np.sqrt(((got - ref) ** 2).sum(0))",
+     "d = np.sqrt(((got - ref) ** 2).sum(1))"),
+    ("dropped square root", "d = np.sqrt(((got - ref) ** 2).sum(0))", "d = ((got - ref) ** 2).sum(0)"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,bad", METRICS_MUTATIONS, ids=[m[0] for m in METRICS_MUTATIONS])
+def test_metric_pins_catch_planted_mistake(tmp_path, name, orig, bad):
+    text = open(METRICS_SRC).read()
+    assert text.count(orig) == 1, f"mutation anchor not unique: {name}"
+    src = tmp_path / "metrics_mut.py"
+    src.write_text(text.replace(orig, bad))
+    env = dict(os.environ, NBODY_METRICS_SRC=str(src))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_metrics.py"], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"
