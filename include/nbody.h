@@ -34,9 +34,11 @@
  *             the halo field if enabled).
  *   Scratch.  Internal scratch grows on first use for a given size; after a
  *             warm-up call with the largest size, later calls allocate
- *             nothing (so they may be captured into a HIP graph).  Outgrown
- *             scratch stays allocated until the context is destroyed, so a
- *             graph captured earlier stays valid.
+ *             nothing (so they may be captured into a HIP graph).  A call
+ *             whose scratch would have to grow while its stream is being
+ *             captured returns NB_EINVAL instead.  Outgrown scratch stays
+ *             allocated until the context is destroyed, so a graph captured
+ *             earlier stays valid.
  *   Threads.  A context is not thread-safe: use one per host thread or lock.
  *             Calls on one context share its scratch, so calls on different
  *             streams of one context must not run concurrently on the device
@@ -141,8 +143,9 @@ typedef struct {
  *         in a spatial (Morton) order: far source tiles use float32
  *         coordinates relative to the tile's centre, subtracted per pair (2)
  *         or through the expanded squared distance (3) (256 lanes, R = 1 or
- *         2, whole system only: nbody_accel_rows returns NB_ENOTSUP; a stream
- *         capture runs the plan as jsrc 0) */
+ *         2, whole system only: nbody_accel_rows returns NB_ENOTSUP).  The
+ *         ordering is the library's own kernels (nbody_spatial_order), so
+ *         these plans can be captured into a HIP graph like the others. */
 typedef struct {
     int32_t R;
     int32_t block;
@@ -264,6 +267,22 @@ NBODY_API nbody_status nbody_surface_density(nbody_ctx *ctx, const nbody_sys *sy
                                              double x0, double y0, double sx, double sy,
                                              uint32_t *counts, void *stream);
 
+/* The spatial order behind the jsrc 2 and 3 plans (the GPU-side design
+ * choice that lets far source tiles use tile-local float32 coordinates; the
+ * paper's kernel keeps the particles' own order).  Writes perm[k] = index of
+ * the particle at sorted position k, for the stable ascending sort of the
+ * 63-bit Morton keys
+ *   key_i = interleave(q_x, q_y, q_z),  q_c = trunc(clamp((c_i - lo_c) * s, 0, 2^21 - 1)),
+ *   s = (2^21 - 1) / max_c(hi_c - lo_c)  (0 if that extent is 0),
+ * lo, hi = the system's bounding box, bit 3b + c of the key = bit b of q_c
+ * (c = 0, 1, 2 for x, y, z); the difference and product are float64, not
+ * fused; NaN coordinates give q = 0.  Equal keys keep index order, so the
+ * result is unique.  perm: DEVICE array of n int32; keys (may be NULL):
+ * DEVICE array of n uint64 that receives the sorted keys.  Reads x, y, z
+ * (m must be non-NULL).  n must be < 2^31. */
+NBODY_API nbody_status nbody_spatial_order(nbody_ctx *ctx, const nbody_sys *sys, int32_t *perm, uint64_t *keys,
+                                           void *stream);
+
 /* ---- many independent systems in one launch ---------------------------- */
 
 /* flags for nbody_batch_create */
@@ -310,7 +329,7 @@ NBODY_API nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, co
  *                      (256 lanes, R = 1 or 2, jsrc 0; or jsrc 2 for NB_MIXED:
  *                      spatial order as for the acceleration, far source tiles
  *                      with tile-local float32 positions and velocities, whole
- *                      systems only, jsrc 0 under stream capture).
+ *                      systems only).
  * Plans of each class are pinned per precision and size class separately. */
 #define NB_PLAN_ACCEL 0x000
 #define NB_PLAN_POTENTIAL 0x100

@@ -138,6 +138,8 @@ hipError_t launch_pair_jerk(const JerkLaunch &J, hipStream_t s);
 // bytes of scratch launch_local_order needs for n particles
 size_t local_order_bytes(int64_t n);
 hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOrder *out, hipStream_t s);
+// the sorted Morton keys inside that scratch (valid after launch_local_order)
+const uint64_t *local_order_keys(const void *scratch, int64_t n);
 hipError_t launch_hermite_predict(const HermitePredict &H, int fp32, hipStream_t s);
 hipError_t launch_rk4(const RK4Launch &K, int fp32, hipStream_t s);
 hipError_t launch_surface_density(const double *x, const double *y, int64_t n, int32_t nx, int32_t ny,

@@ -1,16 +1,18 @@
-// Spatial order of one system for the local mixed pair sum (plans with
-// jsrc = 2): particles sorted along a Morton (Z-order) curve of their
+// Spatial order of one system for the local mixed pair sums (plans with
+// jsrc = 2 and 3): particles sorted along a Morton (Z-order) curve of their
 // positions, so that each tile of 256 consecutive sorted particles is
-// spatially compact, and a bounding box per tile.  The pair kernel then forms
+// spatially compact, and a bounding box per tile.  The pair kernels then form
 // float32 separations from tile-local float32 coordinates for tiles that are
-// far from a workgroup's targets (accel.hip, k_pair_local).
+// far from a workgroup's targets (accel.hip k_pair_local, jerk.hip).
 //
-// Steps, all on the stream: bounding box of the system (two-pass min/max),
-// one 63-bit Morton key per particle, a stable radix sort of (key, index)
-// (hipCUB), a gather of positions and masses into sorted order, and the
-// per-tile boxes.  Deterministic: keys and the stable sort fix the order.
-#include <hipcub/hipcub.hpp>
-
+// Steps, all on the stream and all kernels of this file (no library sort, no
+// memset, no host synchronisation, so the sequence can be captured in a HIP
+// graph): bounding box of the system (two-pass min/max), one 63-bit Morton
+// key per particle, a stable least-significant-digit radix sort of
+// (key, index) in eight passes of 8 bits, a gather of positions and masses
+// into sorted order, and the per-tile boxes.  Every step is integer or
+// min/max work, so the order is deterministic: it is the stable sort of the
+// keys, ties kept in index order.
 #include <algorithm>
 #include <cfloat>
 
@@ -20,7 +22,10 @@ namespace nb {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kParts = 256;  // workgroups of the first bounding-box pass
+constexpr int kParts = 256;        // workgroups of the first bounding-box pass
+constexpr int kBins = 256;         // radix digit of 8 bits
+constexpr int kPasses = 8;         // 8 x 8 bits cover the 63-bit keys
+constexpr int kMaxSortBlocks = 1024;
 
 __device__ __forceinline__ double wmin(double v) {
 #pragma unroll
@@ -107,8 +112,7 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
     return v;
 }
 
-__global__ __launch_bounds__(kT) void k_morton(State st, int64_t n, const double *box, uint64_t *key,
-                                               int32_t *idx) {
+__global__ __launch_bounds__(kT) void k_morton(State st, int64_t n, const double *box, uint64_t *key) {
     // one cubic grid of 2^21 cells per side over the system's box
     const double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
     const double scale = ext > 0.0 ? 2097151.0 / ext : 0.0;
@@ -122,7 +126,126 @@ __global__ __launch_bounds__(kT) void k_morton(State st, int64_t n, const double
             k |= spread3((uint64_t)q) << c;
         }
         key[i] = k;
-        idx[i] = (int32_t)i;
+    }
+}
+
+// ---- stable radix sort of (key, index) ------------------------------------
+// Sort block b owns the keys [b * per * 256, (b + 1) * per * 256).  Per pass:
+// k_sort_hist counts each block's digits, k_sort_scan turns the
+// digit-major table of counts into each block's first output position per
+// digit, and k_sort_scatter moves the keys, tile by tile in input order, to
+// their positions (ranks inside a tile from wave ballots), which keeps equal
+// digits in input order.
+
+__global__ __launch_bounds__(kT) void k_sort_hist(const uint64_t *key, int64_t n, int shift, int64_t per, int nb,
+                                                  uint32_t *hist) {
+    __shared__ uint32_t cnt[kBins];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * per * kT;
+    const int64_t e = std::min<int64_t>(n, b0 + per * kT);
+    for (int64_t i = b0 + threadIdx.x; i < e; i += kT) atomicAdd(&cnt[(uint32_t)(key[i] >> shift) & 0xffu], 1u);
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive prefix sum over the 256 lanes of a workgroup; *total gets the sum.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wsum[kT / 64];
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kT / 64; ++k) {
+        if (k < w) before += wsum[k];
+        all += wsum[k];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+// One workgroup per digit: exclusive scan of that digit's nb block counts
+// (nb <= 1024, four per lane), in place; tot[digit] = the digit's count.
+__global__ __launch_bounds__(kT) void k_sort_scan(uint32_t *hist, int nb, uint32_t *tot) {
+    uint32_t *h = hist + (int64_t)blockIdx.x * nb;
+    const int q = (nb + kT - 1) / kT;
+    const int b = threadIdx.x * q;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (k < q && b + k < nb) ? h[b + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t total = 0;
+    uint32_t run = block_excl_scan(sum, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < q && b + k < nb) h[b + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kT) void k_sort_scatter(const uint64_t *kin, const int32_t *iin, uint64_t *kout,
+                                                     int32_t *iout, int64_t n, int shift, int64_t per, int nb,
+                                                     const uint32_t *hist, const uint32_t *tot) {
+    __shared__ uint32_t run[kBins];
+    __shared__ uint32_t cnt[kT / 64][kBins];
+    const int t = threadIdx.x, w = t / 64, lane = t % 64;
+    {
+        uint32_t total = 0;
+        const uint32_t base = block_excl_scan(tot[t], &total);
+        run[t] = base + hist[(int64_t)t * nb + blockIdx.x];
+    }
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t b0 = (int64_t)blockIdx.x * per * kT;
+    const int64_t e = std::min<int64_t>(n, b0 + per * kT);
+    for (int64_t tile = b0; tile < e; tile += kT) {
+        const int64_t i = tile + t;
+        const bool ok = i < e;
+        const uint64_t k = ok ? kin[i] : 0ull;
+        const int32_t id = ok ? (iin ? iin[i] : (int32_t)i) : 0;
+        const uint32_t d = (uint32_t)(k >> shift) & 0xffu;
+        // lanes of this wave holding a valid key with the same digit
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+#pragma unroll
+        for (int k2 = 0; k2 < kT / 64; ++k2) cnt[k2][t] = 0;
+        __syncthreads();
+        if (ok && rank == 0) cnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            // lane t owns digit t: offsets of the four waves' groups
+            uint32_t r = run[t];
+#pragma unroll
+            for (int k2 = 0; k2 < kT / 64; ++k2) {
+                const uint32_t c = cnt[k2][t];
+                cnt[k2][t] = r;
+                r += c;
+            }
+            run[t] = r;
+        }
+        __syncthreads();
+        if (ok) {
+            const uint32_t pos = cnt[w][d] + rank;
+            kout[pos] = k;
+            iout[pos] = id;
+        }
+        __syncthreads();
     }
 }
 
@@ -148,16 +271,22 @@ inline unsigned grid_for(int64_t n) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t sort_temp_bytes(int64_t n) {
-    size_t bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 63);
-    return bytes;
+// Sort blocks: at most kMaxSortBlocks, each over `per` tiles of 256 keys.
+struct SortShape {
+    int nb;
+    int64_t per;
+};
+SortShape sort_shape(int64_t n) {
+    const int64_t tiles = std::max<int64_t>(1, (n + kT - 1) / kT);
+    const int64_t per = (tiles + kMaxSortBlocks - 1) / kMaxSortBlocks;
+    return {(int)((tiles + per - 1) / per), per};
 }
 
-// Byte offsets of the pieces of the order scratch.
+// Byte offsets of the pieces of the order scratch.  The sort ping-pongs
+// between (key_a, idx_a) and (key_b, idx_b); after its even number of
+// passes the sorted keys and the permutation are in key_a and idx_a.
 struct Layout {
-    size_t key_in, key_out, idx_in, perm, px, py, pz, pm, tbox, parts, box, temp, temp_bytes, total;
+    size_t key_a, key_b, idx_a, idx_b, px, py, pz, pm, tbox, parts, box, hist, tot, total;
 };
 
 Layout layout(int64_t n) {
@@ -166,10 +295,10 @@ Layout layout(int64_t n) {
     const size_t tiles = (nn + kT - 1) / kT;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
-    L.key_in = take(8 * nn);
-    L.key_out = take(8 * nn);
-    L.idx_in = take(4 * nn);
-    L.perm = take(4 * nn);
+    L.key_a = take(8 * nn);
+    L.key_b = take(8 * nn);
+    L.idx_a = take(4 * nn);
+    L.idx_b = take(4 * nn);
     L.px = take(8 * nn);
     L.py = take(8 * nn);
     L.pz = take(8 * nn);
@@ -177,34 +306,51 @@ Layout layout(int64_t n) {
     L.tbox = take(48 * tiles);
     L.parts = take(48 * kParts);
     L.box = take(48);
-    L.temp_bytes = sort_temp_bytes(n);
-    L.temp = take(L.temp_bytes);
+    L.hist = take(4 * (size_t)kBins * sort_shape(n).nb);
+    L.tot = take(4 * kBins);
     L.total = o;
     return L;
 }
 
 }  // namespace
 
+static_assert(kPasses % 2 == 0, "the sorted keys must end in the first buffer");
+
 size_t local_order_bytes(int64_t n) { return layout(n).total; }
+
+const uint64_t *local_order_keys(const void *scratch, int64_t n) {
+    return (const uint64_t *)((const char *)scratch + layout(n).key_a);
+}
 
 hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOrder *out, hipStream_t s) {
     if (n <= 0 || n > INT32_MAX) return hipErrorInvalidValue;
     const Layout L = layout(n);
+    const SortShape S = sort_shape(n);
     char *base = (char *)scratch;
-    uint64_t *key_in = (uint64_t *)(base + L.key_in), *key_out = (uint64_t *)(base + L.key_out);
-    int32_t *idx_in = (int32_t *)(base + L.idx_in), *perm = (int32_t *)(base + L.perm);
+    uint64_t *key_a = (uint64_t *)(base + L.key_a), *key_b = (uint64_t *)(base + L.key_b);
+    int32_t *idx_a = (int32_t *)(base + L.idx_a), *idx_b = (int32_t *)(base + L.idx_b);
     double *px = (double *)(base + L.px), *py = (double *)(base + L.py), *pz = (double *)(base + L.pz);
     double *pm = (double *)(base + L.pm), *tbox = (double *)(base + L.tbox);
     double *parts = (double *)(base + L.parts), *box = (double *)(base + L.box);
+    uint32_t *hist = (uint32_t *)(base + L.hist), *tot = (uint32_t *)(base + L.tot);
     hipLaunchKernelGGL(k_box_partial, dim3(kParts), dim3(kT), 0, s, st, n, parts);
     hipLaunchKernelGGL(k_box_final, dim3(1), dim3(kT), 0, s, parts, kParts, box);
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kT), 0, s, st, n, box, key_in, idx_in);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kT), 0, s, st, n, box, key_a);
+    for (int p = 0; p < kPasses; ++p) {
+        const int shift = 8 * p;
+        const bool even = (p % 2) == 0;
+        const uint64_t *kin = even ? key_a : key_b;
+        uint64_t *kout = even ? key_b : key_a;
+        const int32_t *iin = p == 0 ? nullptr : (even ? idx_a : idx_b);  // first pass: identity
+        int32_t *iout = even ? idx_b : idx_a;
+        hipLaunchKernelGGL(k_sort_hist, dim3(S.nb), dim3(kT), 0, s, kin, n, shift, S.per, S.nb, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kBins), dim3(kT), 0, s, hist, S.nb, tot);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(S.nb), dim3(kT), 0, s, kin, iin, kout, iout, n, shift, S.per, S.nb,
+                           (const uint32_t *)hist, (const uint32_t *)tot);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t temp_bytes = L.temp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(base + L.temp, temp_bytes, key_in, key_out, idx_in, perm, (int)n, 0,
-                                           63, s);
-    if (e != hipSuccess) return e;
+    const int32_t *perm = idx_a;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kT), 0, s, st, n, perm, px, py, pz, pm);
     const int64_t tiles = (n + kT - 1) / kT;
     hipLaunchKernelGGL(k_tile_box, dim3((unsigned)tiles), dim3(kT), 0, s, px, py, pz, n, tbox);

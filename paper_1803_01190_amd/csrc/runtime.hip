@@ -197,8 +197,16 @@ nbody_plan plan_for(nbody_ctx *ctx, int prec, int64_t n) {
     return p;
 }
 
-nbody_status ensure(nbody_ctx *ctx, double **buf, size_t *cap, size_t need) {
+bool capturing(hipStream_t s);
+
+// Grow a scratch buffer to `need` doubles.  Growing allocates, which a
+// stream under capture must not do: such a call fails with NB_EINVAL, and
+// running the same call once before the capture sizes the buffer.
+nbody_status ensure(nbody_ctx *ctx, double **buf, size_t *cap, size_t need, hipStream_t s) {
     if (need <= *cap) return NB_OK;
+    if (capturing(s))
+        return fail(ctx, NB_EINVAL, "library scratch must grow to %zu bytes while the stream is being captured: "
+                    "run the same call once before the capture", need * sizeof(double));
     // grow geometrically so a sequence of growing calls retires little memory
     size_t want = std::max(need, *cap + *cap / 2);
     double *nbuf = nullptr;
@@ -276,19 +284,12 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
     if (P.jsrc >= 2) {
         if (i0 != 0 || i1 != sc.n)
             return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2 or 3) sums whole systems only");
-        if (capturing(s)) {
-            // the ordering uses a library sort; under stream capture the
-            // plan runs with LDS source tiles in the particles' own order
-            nbody_plan p0 = pl;
-            p0.jsrc = 0;
-            return run_pair(ctx, st, sc, i0, i1, mode, p0, kick, hdt, s);
-        }
-        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(sc.n) + 7) / 8);
+        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(sc.n) + 7) / 8, s);
         if (r != NB_OK) return r;
     }
     if (P.split > 1) {
         const size_t need = (size_t)P.split * 4 * (size_t)(i1 - i0);
-        nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, need);
+        nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, need, s);
         if (r != NB_OK) return r;
         P.part = ctx->part;
     }
@@ -449,22 +450,15 @@ nbody_status run_jerk(nbody_ctx *ctx, JerkLaunch &J, const nbody_plan &pl, hipSt
     if (pl.jsrc == 2) {
         if (J.i0 != 0 || J.i1 != J.sc.n)
             return fail(ctx, NB_ENOTSUP, "a spatially ordered jerk plan (jsrc 2) sums whole systems only");
-        if (capturing(s)) {
-            // the ordering uses a library sort; under stream capture the
-            // plan runs with LDS source tiles in the particles' own order
-            nbody_plan p0 = pl;
-            p0.jsrc = 0;
-            return run_jerk(ctx, J, p0, s);
-        }
-        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(J.sc.n) + 7) / 8);
-        if (r == NB_OK) r = ensure(ctx, &ctx->jvel, &ctx->jvel_cap, 3 * (size_t)J.sc.n);
+        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(J.sc.n) + 7) / 8, s);
+        if (r == NB_OK) r = ensure(ctx, &ctx->jvel, &ctx->jvel_cap, 3 * (size_t)J.sc.n, s);
         if (r != NB_OK) return r;
     }
     J.R = pl.R;
     J.block = pl.block;
     J.split = pl.split;
     if (J.split > 1) {
-        nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, (size_t)J.split * 6 * (size_t)rows);
+        nbody_status r = ensure(ctx, &ctx->part, &ctx->part_cap, (size_t)J.split * 6 * (size_t)rows, s);
         if (r != NB_OK) return r;
         J.part = ctx->part;
     }
@@ -660,7 +654,7 @@ nbody_status nbody_step_hermite(nbody_ctx *ctx, nbody_sys *sys, double *jx, doub
         if (n == 0 || nsteps == 0) return NB_OK;
         DevGuard g(ctx->device);
         hipStream_t s = (hipStream_t)stream;
-        r = ensure(ctx, &ctx->integ, &ctx->integ_cap, 6 * (size_t)n);
+        r = ensure(ctx, &ctx->integ, &ctx->integ_cap, 6 * (size_t)n, s);
         if (r != NB_OK) return r;
         double *p = ctx->integ;
         HermitePredict H{};
@@ -710,7 +704,7 @@ nbody_status nbody_step_rk4(nbody_ctx *ctx, nbody_sys *sys, const nbody_params *
         if (n == 0 || nsteps == 0) return NB_OK;
         DevGuard g(ctx->device);
         hipStream_t s = (hipStream_t)stream;
-        r = ensure(ctx, &ctx->integ, &ctx->integ_cap, 12 * (size_t)n);
+        r = ensure(ctx, &ctx->integ, &ctx->integ_cap, 12 * (size_t)n, s);
         if (r != NB_OK) return r;
         double *p = ctx->integ;
         const State st = make_state(sys);
@@ -774,7 +768,7 @@ nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params
         DevGuard g(ctx->device);
         hipStream_t s = (hipStream_t)stream;
         const int64_t n = sys->n;
-        r = ensure(ctx, &ctx->phi, &ctx->phi_cap, (size_t)std::max<int64_t>(n, 1));
+        r = ensure(ctx, &ctx->phi, &ctx->phi_cap, (size_t)std::max<int64_t>(n, 1), s);
         if (r != NB_OK) return r;
         State st = make_state(sys);
         st.phi = ctx->phi;
@@ -817,6 +811,34 @@ nbody_status nbody_surface_density(nbody_ctx *ctx, const nbody_sys *sys, int32_t
         return NB_OK;
     } catch (...) {
         return fail(ctx, NB_ENOMEM, "host exception in nbody_surface_density");
+    }
+}
+
+nbody_status nbody_spatial_order(nbody_ctx *ctx, const nbody_sys *sys, int32_t *perm, uint64_t *keys,
+                                 void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        if (!sys) return fail(ctx, NB_EINVAL, "sys is NULL");
+        if (sys->n < 0 || sys->n > INT32_MAX)
+            return fail(ctx, NB_EINVAL, "n must be in [0, 2^31) (got %lld)", (long long)sys->n);
+        if (sys->n == 0) return NB_OK;
+        if (!sys->x || !sys->y || !sys->z || !sys->m) return fail(ctx, NB_EINVAL, "a position or mass array is NULL");
+        if (!perm) return fail(ctx, NB_EINVAL, "perm is NULL");
+        DevGuard g(ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = sys->n;
+        nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(n) + 7) / 8, s);
+        if (r != NB_OK) return r;
+        LocalOrder lo{};
+        hipError_t e = launch_local_order(make_state(sys), n, ctx->order, &lo, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "spatial order");
+        HIPCHECK(ctx, hipMemcpyAsync(perm, lo.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        if (keys)
+            HIPCHECK(ctx, hipMemcpyAsync(keys, local_order_keys(ctx->order, n), sizeof(uint64_t) * n,
+                                         hipMemcpyDeviceToDevice, s));
+        return NB_OK;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_spatial_order");
     }
 }
 
@@ -994,7 +1016,7 @@ nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys 
         if (!out_dev) return fail(ctx, NB_EINVAL, "out_dev is NULL");
         DevGuard g(ctx->device);
         hipStream_t s = (hipStream_t)stream;
-        r = ensure(ctx, &ctx->phi, &ctx->phi_cap, (size_t)std::max<int64_t>(b->ntot, 1));
+        r = ensure(ctx, &ctx->phi, &ctx->phi_cap, (size_t)std::max<int64_t>(b->ntot, 1), s);
         if (r != NB_OK) return r;
         State st = make_state(all);
         st.phi = ctx->phi;

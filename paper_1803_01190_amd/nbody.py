@@ -80,6 +80,7 @@ def _load():
         "nbody_step_hermite": ([P, S, V, V, V, PR, D, I64, V]),
         "nbody_step_rk4": ([P, S, PR, D, I64, V]),
         "nbody_surface_density": ([P, S, I32, I32, D, D, D, D, V, V]),
+        "nbody_spatial_order": ([P, S, V, V, V]),
         "nbody_batch_create": ([P, I32, ctypes.POINTER(I64), PR, ctypes.POINTER(D), ctypes.c_uint32,
                                 ctypes.POINTER(P)]),
         "nbody_batch_destroy": ([P, P]),
@@ -261,6 +262,18 @@ def nbody_surface_density(ctx, sys: System, nx: int, ny: int, x0: float, y0: flo
                                            float(sx), float(sy), ctypes.c_void_p(out.data_ptr()),
                                            _stream(stream)))
     return out
+
+
+def nbody_spatial_order(ctx, sys: System, stream=None):
+    """(perm, keys): the Morton order of the jsrc 2/3 plans as device tensors
+    (int32 permutation; the sorted uint64 keys held in an int64 tensor)."""
+    dev = sys.t["x"].device
+    perm = torch.empty(sys.n, dtype=torch.int32, device=dev)
+    keys = torch.empty(sys.n, dtype=torch.int64, device=dev)
+    cs = sys.c()
+    _check(ctx, _lib.nbody_spatial_order(ctx, ctypes.byref(cs), ctypes.c_void_p(perm.data_ptr() if sys.n else None),
+                                         ctypes.c_void_p(keys.data_ptr() if sys.n else None), _stream(stream)))
+    return perm, keys
 
 
 def diag_dict(t: torch.Tensor) -> dict:
