@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -102,6 +104,9 @@ def main():
     ap.add_argument("--stop-at", type=int, default=None,
                     help="longrun: stop each run at this step and save it for --resume-dir")
     ap.add_argument("--resume-dir", default=None, help="longrun: continue the runs saved there")
+    ap.add_argument("--stop-after-s", type=float, default=None,
+                    help="longrun: stop each run at its first sample point after this many seconds "
+                         "(from the start of the program) and save it for --resume-dir")
     ap.add_argument("--scaling-max-log2", type=int, default=23, help="scaling: largest N = 2^k")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
     ap.add_argument("--graph", action="store_true", help="serving: replay steps from HIP graphs")
@@ -484,27 +489,38 @@ def bench_longrun(args):
         prm = nb.Params(eps=eps, prec=nb.PREC[prec])
         plan = alt_plan if name == "fp64_alt" else None
         t0 = time.perf_counter()
+        last = [t0]
 
-        def progress(done, rec, name=name, t0=t0):
-            if done % 1000 == 0 or done == steps:
+        def progress(done, rec, name=name, t0=t0, last=last):
+            # every 1000 steps, and at least once a minute for large systems
+            now = time.perf_counter()
+            if done % 1000 == 0 or done == steps or now - last[0] >= 60.0:
+                last[0] = now
                 dv = rec.deviations()
-                log(f"[longrun] {name} step {done}/{steps} ({time.perf_counter() - t0:.0f}s) "
+                log(f"[longrun] {name} step {done}/{steps} ({now - t0:.0f}s) "
                     f"dE {dv['dE_rel'][-1]:.2e} dL {dv['dL_rel'][-1]:.2e} dP {dv['dP_abs'][-1]:.2e}")
 
-        # a run may be cut into pieces (--stop-at, then --resume-dir with the saved piece)
+        # a run may be cut into pieces (--stop-at, then --resume-dir with the
+        # saved piece); pieces are compact snapshots (positions, velocities
+        # and the common mass), whose accelerations are recomputed on load
+        # under the run's plan, which gives the bits the run carried
         run_ic, resume = ic, None
         if args.resume_dir:
             rstem = os.path.join(args.resume_dir, f"resume_{name}_{n}")
-            st, _, _, step, _ = checkpoint.load(rstem + "_state.npz")
+            if plan is not None:
+                nb.nbody_plan_set(ctx.h, prm.prec, n, plan)
+            st, _, _, step, _ = checkpoint.load(rstem + "_state.npz", ctx=ctx.h)
             run_ic = st.numpy()
             del st
             resume = (lr.Record.load(rstem), step)
             log(f"[longrun] {name}: resuming at step {step}")
+        deadline = None if args.stop_after_s is None else T_START + args.stop_after_s
         rec = lr.run(ctx.h, run_ic, prm, dt, steps, every=50, maps_at=maps_at, grid=grid, plan=plan,
-                     progress=progress, resume=resume, stop_at=args.stop_at)
+                     progress=progress, resume=resume, stop_at=args.stop_at, deadline=deadline)
         if rec.done < steps:
             stem = os.path.join(args.out_dir, f"resume_{name}_{n}")
-            checkpoint.save(stem + "_state.npz", nb.System.from_arrays(rec.final), prm, step=rec.done)
+            checkpoint.save(stem + "_state.npz", nb.System.from_arrays(rec.final), prm, step=rec.done,
+                            compact=True)
             rec.save(stem)
             log(f"[longrun] {name}: stopped at step {rec.done}, saved {stem}*")
         recs[name] = rec

@@ -95,7 +95,7 @@ class Record:
 
 def run(ctx, ic: dict, prm: "nb.Params", dt: float, steps: int, every: int = 50, maps_at=(),
         grid: Grid | None = None, plan: dict | None = None, progress=None, resume=None,
-        stop_at: int | None = None) -> Record:
+        stop_at: int | None = None, deadline: float | None = None) -> Record:
     """Integrate ``ic`` for ``steps`` leapfrog steps of ``dt``, sampling the
     diagnostics every ``every`` steps (and at 0) and a surface-density map at
     each step count in ``maps_at``.  ``plan`` pins the launch plan of the
@@ -105,7 +105,9 @@ def run(ctx, ic: dict, prm: "nb.Params", dt: float, steps: int, every: int = 50,
     (``Record.done`` tells where), and ``resume=(record, step)`` continues
     from a record and a state saved at ``step`` (``ic`` then holds that
     state, accelerations included, as ``checkpoint`` writes it); the pieces
-    take the same steps as one run, bit for bit."""
+    take the same steps as one run, bit for bit.  ``deadline`` (a
+    ``time.perf_counter()`` value) also ends the run early, at the first
+    sample point reached after it."""
     grid = grid or Grid()
     s = nb.System.from_arrays(ic)
     n = s.n
@@ -143,6 +145,8 @@ def run(ctx, ic: dict, prm: "nb.Params", dt: float, steps: int, every: int = 50,
                 rec.maps[done] = _map(ctx, s, grid)
             if progress is not None:
                 progress(done, rec)
+            if deadline is not None and time.perf_counter() >= deadline and done % every == 0:
+                break
         rec.final = s.numpy()
         rec.done = done
         return rec

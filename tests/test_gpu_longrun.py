@@ -77,3 +77,44 @@ def test_stop_and_resume_bitwise(nb, ctx, tmp_path):
         assert np.array_equal(rest.maps[k], whole.maps[k])
     for k in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az"):
         assert np.array_equal(rest.final[k], whole.final[k]), k
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32", "fp64"])
+def test_compact_resume_bitwise(nb, ctx, tmp_path, prec):
+    # a compact snapshot (positions, velocities, the common mass) recomputes
+    # the accelerations on load; under a spatially ordered mixed plan and the
+    # plain plans alike the resumed run takes the same steps, bit for bit
+    from paper_1803_01190_amd import checkpoint
+    from paper_1803_01190_amd import longrun as lr
+    n, steps, every, eps = 3000, 40, 10, 0.02
+    dt = wl.outer_period(halo=wl.no_halo()) / 4000.0
+    ic = wl.make("disk_sg", n, 9)
+    prm = nb.Params(eps=eps, prec=nb.PREC[prec])
+    plan = {"R": 1, "block": 256, "split": 2, "jsrc": 3} if prec == "mixed" else None
+    print(f"[case] compact resume {prec} n={n} plan={plan}", flush=True)
+    grid = lr.Grid(32, 32, -6.0, -6.0, 12.0 / 32)
+    whole = lr.run(ctx, ic, prm, dt, steps, every=every, maps_at=(0, steps), grid=grid, plan=plan)
+    first = lr.run(ctx, ic, prm, dt, steps, every=every, maps_at=(0, steps), grid=grid, plan=plan, stop_at=20)
+    stem = str(tmp_path / "piece")
+    checkpoint.save(stem + "_state.npz", nb.System.from_arrays(first.final), prm, step=first.done, compact=True)
+    first.save(stem)
+    with np.load(stem + "_state.npz", allow_pickle=False) as z:
+        assert "ax" not in z.files and "m" not in z.files
+    with pytest.raises(ValueError):
+        checkpoint.load(stem + "_state.npz")
+    if plan is not None:
+        nb.nbody_plan_set(ctx, prm.prec, n, plan)
+    try:
+        st, _, _, step, _ = checkpoint.load(stem + "_state.npz", ctx=ctx)
+    finally:
+        if plan is not None:
+            nb.nbody_plan_set(ctx, prm.prec, n, None)
+    got = st.numpy()
+    for k in ("ax", "ay", "az"):
+        assert np.array_equal(got[k], first.final[k]), k
+    rest = lr.run(ctx, got, prm, dt, steps, every=every, maps_at=(0, steps), grid=grid, plan=plan,
+                  resume=(lr.Record.load(stem), step))
+    assert rest.E == whole.E and rest.Lz == whole.Lz and rest.P == whole.P
+    assert np.array_equal(rest.maps[steps], whole.maps[steps])
+    for k in ("x", "vx", "az"):
+        assert np.array_equal(rest.final[k], whole.final[k]), k
