@@ -32,6 +32,14 @@ METRIC = "pair-interactions/s at N=2^20 (FP64 vs mixed @ stated err); p50/p99 la
 FLOPS_PER_INTERACTION = 20  # conventional count for the softened pair term
 JERK_FLOPS_PER_INTERACTION = 42  # the 20 above + relative velocity (3), r.u (5), factor (2), jerk FMAs (12)
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3, "fp32": 157.3}  # MI355X vector peaks
+# VALU issue quad-cycles per lane-interaction of each precision's tuned pair
+# kernel after dual issue (SQ counters on the N = 2^20 disk,
+# profiles/pmc_valu_disk_2p20.md); 1024 SIMDs each issue one wave64
+# instruction per quad-cycle, so the issue-limited rate is 16384 f / qc at
+# clock f (the 2.4 GHz peak clock is used).
+ISSUE_QC = {"fp64": 18.07, "mixed": 9.57, "fp32": 10.28}
+PEAK_CLOCK_HZ = 2.4e9
+MIN_LATENCY_SAMPLES = 50
 DTYPE = {"fp64": "f64", "mixed": "f32 pair / f64 accumulate+state", "fp32": "f32"}
 KERNEL_SOURCES = ["paper_1803_01190_amd/csrc/accel.hip", "paper_1803_01190_amd/csrc/order.hip",
                   "paper_1803_01190_amd/csrc/nbody_internal.h"]
@@ -108,8 +116,15 @@ def main():
                     help="longrun: stop each run at its first sample point after this many seconds "
                          "(from the start of the program) and save it for --resume-dir")
     ap.add_argument("--scaling-max-log2", type=int, default=23, help="scaling: largest N = 2^k")
-    ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
-    ap.add_argument("--graph", action="store_true", help="serving: replay steps from HIP graphs")
+    ap.add_argument("--requests", type=int, default=12, help="serving: requests per arrival rate")
+    ap.add_argument("--no-graph", action="store_true", help="serving: launch every step (no HIP graph replay)")
+    ap.add_argument("--serve-log2", default="12-20", help="serving: request sizes N = 2^lo .. 2^hi (log-uniform)")
+    ap.add_argument("--serve-steps", default="10-1000", help="serving: steps per request (uniform)")
+    ap.add_argument("--rates", default="0.5,0.9,1.1", help="serving: arrival rates as fractions of capacity")
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="serving: capacity in requests/s (skip its measurement)")
+    ap.add_argument("--serve-out", default=None, help="serving: also write the result JSON here")
+    ap.add_argument("--integ-out", default=None, help="integrators: also write the result JSON here")
     ap.add_argument("--profile-run", action="store_true",
                     help="run for counter collection: no CPU baseline, plus a copy kernel of "
                          "known size to calibrate FETCH_SIZE / WRITE_SIZE")
@@ -198,6 +213,16 @@ def main():
         prof = nb.nbody_profile_read(ctx.h)
         d1 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
         step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+        if prec == precs[0] and args.steps < MIN_LATENCY_SAMPLES:
+            # more per-step latency samples for p50/p99, after the timed region
+            extra = MIN_LATENCY_SAMPLES - args.steps
+            ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(extra + 1)]
+            ev2[0].record()
+            for k in range(extra):
+                nb.nbody_step_kdk(ctx.h, s, prm, dt, 1)
+                ev2[k + 1].record()
+            torch.cuda.synchronize()
+            step_ms += [ev2[k].elapsed_time(ev2[k + 1]) for k in range(extra)]
         wall = w1 - w0
         inter = float(n) * float(n)
         rate = args.steps * inter / wall
@@ -207,7 +232,8 @@ def main():
         results[prec] = {
             "value": rate,
             "ms_per_step": 1e3 * wall / args.steps,
-            "latency_ms": {"p50": percentile(step_ms, 0.5), "p99": percentile(step_ms, 0.99)},
+            "latency_ms": {"p50": percentile(step_ms, 0.5), "p99": percentile(step_ms, 0.99),
+                           "samples": len(step_ms)},
             "plan": plan,
             "accel_kernel_ms": accel_ms,
             "accel_launches": prof["accel_launches"],
@@ -291,6 +317,18 @@ def main():
                        if r0["plan"].get("jsrc") in (2, 3) else "pair sum (k_pair)"),
             "flops_per_interaction": FLOPS_PER_INTERACTION,
             "interactions_per_launch": float(n) * float(n),
+        },
+        # the binding limit of this VALU-bound kernel: its instruction issue
+        "issue_roofline": {
+            "bound": "valu issue",
+            "unit": "pair-interactions/s",
+            "achieved": float(n) * float(n) / (r0["accel_kernel_ms"] * 1e-3),
+            "peak": 16384.0 * PEAK_CLOCK_HZ / ISSUE_QC[head],
+            "frac": float(n) * float(n) / (r0["accel_kernel_ms"] * 1e-3) / (16384.0 * PEAK_CLOCK_HZ / ISSUE_QC[head]),
+            "quad_cycles_per_interaction": ISSUE_QC[head],
+            "clock_hz": PEAK_CLOCK_HZ,
+            "source": "SQ_ACTIVE_INST_VALU / SQ_ACTIVE_INST_VALU2 counts of the pair kernel, "
+                      "profiles/pmc_valu_disk_2p20.md",
         },
         "cpu_baseline": cpu,
         "force_error": force_err or None,
@@ -379,7 +417,11 @@ def bench_integrators(args):
     two acceleration sums).  The long-run
     reference is the float64 O4 run at dt = 5e-4 on the GPU (its pair sum is
     the float64 path gated against the CPU oracle at 1e-12); the CPU oracle
-    would need hours for these runs."""
+    would need hours for these runs.  The CPU-baseline leg runs the oracle
+    on 1024 sampled rows at every checkpoint of the reference run (each row
+    summed over all N sources) and compares them with the reference's own
+    float64 accelerations there (gate 1e-12, conditioned), which both times
+    the oracle and pins the reference trajectory's forces."""
     import numpy as np
     import torch
 
@@ -395,7 +437,7 @@ def bench_integrators(args):
     def params(prec):
         return nb.Params(eps=0.02, prec=nb.PREC[prec], halo=True, halo_v2=h.v2, halo_rc=h.rc)
 
-    def run(prec, scheme, nsteps, every):
+    def run(prec, scheme, nsteps, every, check=None):
         prm = params(prec)
         s = nb.System.from_arrays(ic)
         nb.nbody_accel(ctx.h, s, prm)
@@ -416,6 +458,8 @@ def bench_integrators(args):
             torch.cuda.synchronize()
             busy += time.perf_counter() - t0
             done += k
+            if check is not None:
+                check(done, s)
             d = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
             worst["dE_rel"] = max(worst["dE_rel"], abs(d["E"] - d0["E"]) / abs(d0["E"]))
             worst["dLz_rel"] = max(worst["dLz_rel"], abs(d["Lz"] - d0["Lz"]) / abs(d0["Lz"]))
@@ -431,8 +475,35 @@ def bench_integrators(args):
     ref_a = f["fp64"]
     ferr = {p: float(np.sqrt(np.mean(((f[p] - ref_a) ** 2).sum(0) / (ref_a ** 2).sum(0)))) for p in ("mixed", "fp32")}
     log(f"[bench] rms relative force error vs fp64 at t=0: {ferr}")
-    ref, _, tref = run("fp64", "o4", 2000, 100)
-    log(f"[bench] reference fp64 o4 dt=5e-4 done in {tref:.1f}s")
+    checks = []
+    cpu = {"s": 0.0, "pairs": 0.0, "threads": None}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.metrics import force_errors
+
+        rows = np.sort(np.random.default_rng(17).choice(n, size=1024, replace=False))
+        halo = oracle.Halo(h.v2, h.rc)
+
+        def check(step, s):
+            # the oracle at the reference's current positions (1024 rows)
+            st = {k: s[k].cpu().numpy() for k in ("x", "y", "z", "m", "ax", "ay", "az")}
+            t0 = time.perf_counter()
+            ax, ay, az, A = oracle.accel(st["x"], st["y"], st["z"], st["m"], 1.0, 0.02, rows=rows, want_scale=True)
+            cpu["s"] += time.perf_counter() - t0
+            cpu["pairs"] += float(rows.size) * n
+            cpu["threads"] = oracle.max_threads()
+            hx, hy, hz = oracle.halo_accel(st["x"][rows], st["y"][rows], st["z"][rows], halo)
+            A = A + np.sqrt(hx * hx + hy * hy + hz * hz)
+            e = force_errors(np.stack([st["ax"][rows], st["ay"][rows], st["az"][rows]]),
+                             np.stack([ax + hx, ay + hy, az + hz]), A)
+            checks.append({"step": step, **e})
+            if not (e["eps_cond"] <= 1e-12 and e["eps_rms"] <= 1e-12):
+                raise RuntimeError(f"reference run at step {step}: float64 force error {e} above 1e-12")
+    else:
+        check = None
+    ref, _, tref = run("fp64", "o4", 2000, 100, check=check)
+    log(f"[bench] reference fp64 o4 dt=5e-4 done in {tref:.1f}s; oracle checks {len(checks)}, worst eps_cond "
+        f"{max((c['eps_cond'] for c in checks), default=float('nan')):.2e}")
     runs = {}
     evals_per_step = {"kdk": 1, "o4": 3, "hermite": 1, "rk4": 4}
     for prec in ("fp64", "mixed", "fp32"):
@@ -450,9 +521,18 @@ def bench_integrators(args):
            "ms_per_step": 1e3 * runs["mixed_kdk_1000"]["wall_s"] / 1000, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE["mixed"], "data": "synthetic",
            "config": {"workload": "exponential disk N=2^17 + halo, eps=0.02, T=1; reference fp64 O4 dt=5e-4 "
-                                  "on the GPU", "n": n},
-           "force_error_rms_vs_fp64": ferr, "runs": runs}
+                                  "on the GPU", "n": n,
+                      "plans": {k: nb.nbody_plan_get(ctx.h, nb.plan_code(k), n)
+                                for k in ("fp64", "mixed", "fp32", "fp64/jerk", "mixed/jerk", "fp32/jerk")}},
+           "force_error_rms_vs_fp64": ferr, "runs": runs,
+           "reference_check": {"rows": 1024, "gate": 1e-12, "checkpoints": checks},
+           "cpu_baseline": None if not checks else {
+               "value": cpu["pairs"] / cpu["s"], "unit": "pair-interactions/s", "cores": cpu["threads"],
+               "kind": "oracle", "sample": f"1024 rows x {n} sources at each of {len(checks)} checkpoints"}}
     print(json.dumps(res))
+    if args.integ_out:
+        with open(args.integ_out, "w") as f:
+            json.dump(res, f, indent=1)
     ctx.close()
 
 
@@ -602,6 +682,16 @@ def bench_hermite(args):
         prof = nb.nbody_profile_read(ctx.h)
         d1 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
         step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+        if prec == precs[0] and args.steps < MIN_LATENCY_SAMPLES:
+            # more per-step latency samples for p50/p99, after the timed region
+            extra = MIN_LATENCY_SAMPLES - args.steps
+            ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(extra + 1)]
+            ev2[0].record()
+            for k in range(extra):
+                nb.nbody_step_kdk(ctx.h, s, prm, dt, 1)
+                ev2[k + 1].record()
+            torch.cuda.synchronize()
+            step_ms += [ev2[k].elapsed_time(ev2[k + 1]) for k in range(extra)]
         inter = float(n) * float(n)
         pair_ms = prof["accel_ms"] / max(prof["accel_launches"], 1)
         tflops = JERK_FLOPS_PER_INTERACTION * inter / (pair_ms * 1e-3) / 1e12
@@ -724,9 +814,14 @@ def bench_scaling(args):
 
 
 def bench_serving(args):
-    """Poisson request stream through the continuous-batching loop.  Request
-    sizes are capped for a run of minutes: N log-uniform in [2^12, 2^16],
-    steps uniform in [10, 100], Plummer or disk, mixed with 10% FP64."""
+    """Poisson request stream through the continuous-batching loop: N
+    log-uniform in [2^lo, 2^hi] (default [2^12, 2^20]), steps uniform in
+    [10, 1000], Plummer or disk with equal odds, mixed with 10% FP64
+    (--serve-* options narrow it).  The capacity mu (requests/s with every
+    request arriving at once) is measured first unless --capacity gives it;
+    then each rate of --rates (fractions of mu) runs the same requests with
+    Poisson arrival times scaled to that rate.  Reports completed requests/s,
+    pair-interactions/s and p50/p99 latency (arrival to result on the host)."""
     import torch
 
     import workloads as wl
@@ -734,46 +829,73 @@ def bench_serving(args):
     from paper_1803_01190_amd.serving import GpuBackend, Request, Scheduler
 
     ctx = nb.Context(0)
+    nb.load_plans(ctx.h)
     nreq = args.requests
+    lo, _, hi = args.serve_log2.partition("-")
+    slo, _, shi = args.serve_steps.partition("-")
+    lo, hi, slo, shi = int(lo), int(hi), int(slo), int(shi)
 
     # the requests' initial conditions are prepared by the client before
     # they arrive (outside the timed runs); arrival times are rescaled per rate
-    base = wl.request_stream(nreq, seed=5, rate=1.0, lo_log2=12, hi_log2=16, steps_lo=10, steps_hi=100,
+    base = wl.request_stream(nreq, seed=5, rate=1.0, lo_log2=lo, hi_log2=hi, steps_lo=slo, steps_hi=shi,
                              fp64_fraction=0.1)
     ics = [wl.make(r["model"], r["n"], r["seed"]) for r in base]
+    work = sum(float(r["n"]) ** 2 * r["steps"] for r in base)
+    log(f"[bench] serving: {nreq} requests, N in [2^{lo}, 2^{hi}], steps in [{slo}, {shi}], "
+        f"{work:.3e} pair-interactions in all")
 
     def make(rate):
         return [Request(id=r["id"], t_arrive=r["t_arrive"] / rate, n=r["n"], steps=r["steps"], model=r["model"],
                         fp64=r["fp64"], seed=r["seed"], ic=ics[k]) for k, r in enumerate(base)]
 
     budget = 64 << 30
-    graph = args.graph
-    # capacity: everything arrives at once
-    be = GpuBackend(ctx.h, keep_state=False, graph=graph, diagnostics=False)
-    cap = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(1e9)).summary()
-    be.close()
-    mu = cap["requests_per_s"]
-    log(f"[bench] serving capacity {mu:.2f} req/s ({cap})")
-    sweep = []
-    for frac in (0.25, 0.5, 0.75, 0.9, 1.1):
+    graph = not args.no_graph
+    last = [0.0]
+
+    def progress(info, tag=""):
+        if info["t"] - last[0] >= 30.0:
+            last[0] = info["t"]
+            log(f"[serving{tag}] t={info['t']:.0f}s done {info['done']}/{nreq} active {info['active']} "
+                f"waiting {info['waiting']} pending {info['pending']} HBM {info['used_bytes'] / 2**30:.1f} GiB")
+
+    def run(rate, tag):
+        last[0] = 0.0
         be = GpuBackend(ctx.h, keep_state=False, graph=graph, diagnostics=False)
-        smry = Scheduler(be, hbm_budget=budget, max_tick_steps=10).run(make(frac * mu)).summary()
+        sch = Scheduler(be, hbm_budget=budget, max_tick_steps=25, progress=lambda i: progress(i, tag))
+        smry = sch.run(make(rate)).summary()
         be.close()
+        return smry, be.plan
+
+    plan = None
+    if args.capacity:
+        mu, cap = args.capacity, None
+    else:
+        cap, plan = run(1e9, " capacity")
+        mu = cap["requests_per_s"]
+        log(f"[bench] serving capacity {mu:.4f} req/s ({cap})")
+    sweep = []
+    for frac in [float(f) for f in args.rates.split(",") if f]:
+        smry, plan = run(frac * mu, f" {frac:.2f} mu")
         smry["rate_req_per_s"] = frac * mu
         smry["rate_frac"] = frac
         sweep.append(smry)
         log(f"[bench] serving rate {frac:.2f} mu: {smry}")
     torch.cuda.synchronize()
-    mid = sweep[2]
+    head = sweep[len(sweep) // 2] if sweep else cap
     res = {"metric": "serving throughput (requests/s, pair-interactions/s) and p50/p99 latency",
-           "value": mid["interactions_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,
+           "value": head["interactions_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,
            "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": DTYPE["mixed"], "data": "synthetic",
-           "config": {"workload": f"{nreq} Poisson-arriving requests per rate, N log-uniform in [2^12, 2^16], "
-                                  "steps uniform in [10, 100], Plummer or disk, 10% FP64, HBM budget 64 GiB",
-                      "capacity_req_per_s": mu, "graph_replay": graph},
-           "latency_s": mid["latency_s"], "capacity": cap, "sweep": sweep}
+           "config": {"workload": f"{nreq} Poisson-arriving requests per rate, N log-uniform in [2^{lo}, 2^{hi}], "
+                                  f"steps uniform in [{slo}, {shi}], Plummer or disk, 10% FP64, HBM budget 64 GiB",
+                      "capacity_req_per_s": mu, "graph_replay": graph,
+                      "batch_plan": plan,
+                      "requests": [{k: r[k] for k in ("n", "steps", "model", "fp64")} for r in base]},
+           "latency_s": head["latency_s"], "capacity": cap, "sweep": sweep}
     print(json.dumps(res))
+    if args.serve_out:
+        with open(args.serve_out, "w") as f:
+            json.dump(res, f, indent=1)
     ctx.close()
 
 

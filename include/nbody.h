@@ -184,11 +184,24 @@ NBODY_API nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const n
  * are sources).  Rows [i0, i1) are bitwise equal to those of nbody_accel
  * under the same plan; the other rows are untouched.  This is one GPU's
  * share when the targets of one system are split across several GPUs.
- * A spatially ordered plan (jsrc 2 or 3) sums whole systems only: a proper
- * subrange under such a plan returns NB_ENOTSUP (pin a jsrc 0 or 1 plan for
- * the size class to use row ranges). */
+ * A spatially ordered plan (jsrc 2 or 3) takes its targets in its own
+ * order: a proper subrange of particle indices under such a plan returns
+ * NB_ENOTSUP; nbody_accel_order_rows takes ranges of that order. */
 NBODY_API nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                               int64_t i0, int64_t i1, void *stream);
+
+/* The i-split of the paper's Section 2 (each GPU sums its share of the
+ * targets against all sources) for a spatially ordered plan (jsrc 2 or 3),
+ * whose targets are taken in the system's Morton order: the accelerations of
+ * the particles at sorted positions k in [k0, k1) (particles perm[k], see
+ * nbody_spatial_order), bitwise equal to those of nbody_accel under the same
+ * plan; other particles' accelerations are untouched.  The order is
+ * recomputed from all n positions on every call (as each GPU of a split
+ * would, from the gathered positions).  NB_ENOTSUP when the plan for
+ * (prec, n) is not spatially ordered, or sys->phi is not NULL; NB_EINVAL for
+ * a range outside [0, n). */
+NBODY_API nbody_status nbody_accel_order_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+                                              int64_t k0, int64_t k1, void *stream);
 
 /* Eqs. (5)-(7): nsteps leapfrog steps of size dt,
  *   v += dt/2 a;  r += dt v;  a = accel(r);  v += dt/2 a
@@ -297,13 +310,48 @@ NBODY_API nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64
                                 const nbody_params *prm, const double *dt, uint32_t flags,
                                 nbody_batch **out);
 NBODY_API nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *batch);
-/* The pair-sum plan used for every system of the batch. */
+/* Replace the batch's systems by another set (same arguments and checks as
+ * nbody_batch_create; the batch keeps its plan): the continuous-batching
+ * form, for a serving loop whose active set changes.  The batch's device
+ * tables are reused when large enough (grow-only) and the new ones are
+ * copied from pinned host staging memory in the order of `stream`, without
+ * synchronising the device; work on the batch must then be issued on
+ * `stream` (or after synchronising it).  The call waits only for the
+ * previous reset's copies to have left the staging memory.  Cached graphs
+ * are dropped (they are re-captured on the next graph step).  Not allowed
+ * under stream capture (NB_EINVAL). */
+NBODY_API nbody_status nbody_batch_reset(nbody_ctx *ctx, nbody_batch *batch, int32_t B, const int64_t *off,
+                                         const nbody_params *prm, const double *dt, void *stream);
+/* The batch plan (a batch is the multi-system form of the paper's Section 2
+ * tiling: work items are (system, tile of R * 256 targets, chunk of sources)):
+ *   R      targets per lane (1 or 2), block 256;
+ *   split  source tiles of 256 per chunk: a system of n particles is summed
+ *          in ceil(n / (256 split)) chunks whose partial sums are reduced in
+ *          a fixed order (0: whole systems, no chunks; float32 systems never
+ *          split);
+ *   jsrc   for the NB_MIXED systems: 0 (LDS source tiles) or 2, 3 (the
+ *          batch in spatial order, far tiles in the tile-local float32 forms
+ *          of the single-system plans with the same jsrc).
+ * nbody_batch_create takes the plan pinned with class NB_PLAN_BATCH for
+ * (NB_MIXED, the batch's largest n), else {1, 256, 32, 3}. */
 NBODY_API nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *batch, nbody_plan *out);
+/* Replace the batch's plan (rebuilds its work lists and scratch: allocates
+ * and synchronises the device; drops cached graphs).  NB_EINVAL for an
+ * unsupported plan. */
+NBODY_API nbody_status nbody_batch_set_plan(nbody_ctx *ctx, nbody_batch *batch, const nbody_plan *plan);
+/* The single-system plan under which nbody_accel (and the single-system
+ * steps) on system `sys` alone give bitwise the batch's results for it:
+ * {R, 256, that system's chunk count, jsrc (0 unless the system is summed in
+ * spatial order)}. */
+NBODY_API nbody_status nbody_batch_system_plan(nbody_ctx *ctx, const nbody_batch *batch, int32_t sys,
+                                               nbody_plan *out);
 
-/* Pair sums of every system of the batch in one persistent launch per
- * precision present.  all->n must equal off[B].  Each system's result is
- * bitwise equal to nbody_accel on that system alone under the plan that
- * nbody_batch_get_plan reports (split is always 1 in a batch). */
+/* Pair sums of every system of the batch: the batch's spatial order when it
+ * has systems summed in it, one persistent launch per work list (per
+ * precision, plus the spatially ordered NB_MIXED systems) and one fixed-order
+ * reduction of the chunk sums.  all->n must equal off[B].  Each system's
+ * result is bitwise equal to nbody_accel on that system alone under the plan
+ * that nbody_batch_system_plan reports. */
 NBODY_API nbody_status nbody_accel_batched(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
                                  void *stream);
 /* nsteps KDK steps of every system with its own dt (same contract as
@@ -334,6 +382,7 @@ NBODY_API nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *batch, co
 #define NB_PLAN_ACCEL 0x000
 #define NB_PLAN_POTENTIAL 0x100
 #define NB_PLAN_JERK 0x200
+#define NB_PLAN_BATCH 0x300  /* batch plans (see nbody_batch_get_plan), keyed by the largest system */
 
 /* Plan the single-system pair sum uses for (prec, n).  Plans are keyed by
  * (prec, ceil(log2 n)); an untuned key gets a fixed heuristic plan. */
@@ -341,16 +390,34 @@ NBODY_API nbody_status nbody_plan_get(nbody_ctx *ctx, int32_t prec, int64_t n, n
 /* Pin the plan for the key of (prec, n) (e.g. one loaded from a cache file);
  * plan == NULL removes the pinned plan so the heuristic applies again. */
 NBODY_API nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, const nbody_plan *plan);
-/* Time every candidate plan on synthetic particles of size n on `device`
- * scratch memory, pin the fastest for the key of (prec, n) and return it.
- * Synchronous.  budget_ms > 0 bounds the time spent (at least one
- * candidate is always timed).  Candidates are the jsrc 0 and 1 plans plus
- * the key's current plan; above n = 32768 the candidates sweep only the
- * first 32768 sources, so a current spatially ordered plan (jsrc 2 or 3,
- * whose speed also depends on how the particles are distributed) is not
- * timed there and the result is a jsrc 0 or 1 plan. */
+/* Autotuning (synchronous).  Each candidate plan of the class is timed on
+ * whole systems (all n sources; one warm-up and two timed launches) until
+ * budget_ms is spent (<= 0: every candidate; at least one is always timed;
+ * each is timed over 2 to 16 launches, at least 20 ms when launches allow);
+ * the fastest is pinned for the key of (prec, n) and returned.  Candidates:
+ * the key's current plan first, then for NB_MIXED the spatially ordered
+ * plans (jsrc 3 and 2: accelerations; jsrc 2: jerk), then every R, block
+ * (the j-tile length) and power-of-two split up to 64 (chunks of at least
+ * two source tiles) the kernels take.  Kernel loop
+ * unrolling is fixed at build time (four sources per step of an LDS tile
+ * sweep, eight per scalar group).
+ * nbody_autotune times them on a synthetic thin exponential disk of n
+ * particles (the spatially ordered plans' speed depends on the particle
+ * distribution); nbody_autotune_sys on the caller's system, whose
+ * accelerations (and nothing else) it overwrites with those of the chosen
+ * plan (class NB_PLAN_JERK needs velocities; its jerks and the potential
+ * class's phi go to temporary memory). */
 NBODY_API nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, double budget_ms,
                             nbody_plan *out);
+NBODY_API nbody_status nbody_autotune_sys(nbody_ctx *ctx, int32_t prec, const nbody_sys *sys,
+                                          const nbody_params *prm, double budget_ms, nbody_plan *out);
+/* Time batch plans (R 1 and 2; jsrc 3, 2 and 0 when the batch has NB_MIXED
+ * systems; chunks of 0, 8, 16, 32 and 64 source tiles) with
+ * nbody_accel_batched on the caller's state, set the fastest on the batch,
+ * pin it (class NB_PLAN_BATCH, keyed by the largest system) and leave the
+ * accelerations as it gives them.  Synchronous; rebuilds the batch's tables. */
+NBODY_API nbody_status nbody_batch_autotune(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,
+                                            double budget_ms, nbody_plan *out);
 
 /* ---- profiling ---------------------------------------------------------- */
 

@@ -574,27 +574,35 @@ __device__ __forceinline__ void interact_local(Lane<P_MIXED, R> &L, const JL &e,
     }
 }
 
-template <int R, bool SAFE, bool EXP>
-__global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk) {
-    constexpr int BLOCK = 256;
-    __shared__ JL ftile[BLOCK];
-    __shared__ JM dtile[BLOCK];
-    __shared__ float fmass[EXP ? BLOCK : 1];
-    const LocalOrder &O = P.lo;
-    const int64_t n = P.sc.n;
-    const int64_t ib = (int64_t)blockIdx.x * (BLOCK * R);  // sorted positions, all n targets
-    const int64_t jb = (int64_t)blockIdx.y * chunk;
-    const int64_t je = (jb + chunk < n) ? jb + chunk : n;
-    const int t = threadIdx.x;
-    State sv{};  // the sorted positions and masses, read-only
+// The spatially ordered arrays of one system (indices relative to its first
+// sorted particle) and its tile boxes.
+struct LocalSys {
+    const double *px, *py, *pz, *pm, *tbox;
+    int64_t n;
+};
+
+__device__ __forceinline__ State sorted_state(const LocalSys &O) {
+    State sv{};  // read-only view of the sorted positions and masses
     sv.x = const_cast<double *>(O.px);
     sv.y = const_cast<double *>(O.py);
     sv.z = const_cast<double *>(O.pz);
     sv.m = O.pm;
-    Lane<P_MIXED, R> L;
-    lane_init<P_MIXED, R>(L, sv, ib, n, BLOCK);
+    return sv;
+}
+
+// Sum the sorted sources [jb, je) of one system into the lanes holding the
+// R * 256 sorted targets from ib.  Far tiles (box farther from the targets'
+// box than its own diagonal) take the tile-local float32 forms, the others
+// the mixed pair term on float64-formed separations.
+template <int R, bool SAFE, bool EXP>
+__device__ __forceinline__ void local_sweep(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t ib, int64_t jb,
+                                            int64_t je, double eps2, float eps2f, JL *ftile, JM *dtile,
+                                            float *fmass) {
+    constexpr int BLOCK = 256;
+    const int t = threadIdx.x;
+    const State sv = sorted_state(O);
     // box of this workgroup's targets: the boxes of its R tiles
-    const int64_t ntile = (n + BLOCK - 1) / BLOCK;
+    const int64_t ntile = (O.n + BLOCK - 1) / BLOCK;
     double bmin[3] = {1.0e308, 1.0e308, 1.0e308}, bmax[3] = {-1.0e308, -1.0e308, -1.0e308};
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -635,7 +643,7 @@ __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk)
             for (int r = 0; r < R; ++r) {
                 const double dx = L.xi[r] - ctr[0], dy = L.yi[r] - ctr[1], dz = L.zi[r] - ctr[2];
                 wx[r] = (float)(-2.0 * dx); wy[r] = (float)(-2.0 * dy); wz[r] = (float)(-2.0 * dz);
-                qi[r] = (float)(dx * dx + dy * dy + dz * dz + P.sc.eps2);
+                qi[r] = (float)(dx * dx + dy * dy + dz * dz + eps2);
             }
             const double m0 = O.pm[jt];
             const bool um = __syncthreads_and(mj == m0) != 0;
@@ -667,10 +675,10 @@ __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk)
             const bool um = __syncthreads_and(e.m == m0) != 0;
             if (um) {
 #pragma unroll 4
-                for (int k = 0; k < BLOCK; ++k) interact_local<R, SAFE, true>(L, ftile[k], rx, ry, rz, P.sc.eps2f);
+                for (int k = 0; k < BLOCK; ++k) interact_local<R, SAFE, true>(L, ftile[k], rx, ry, rz, eps2f);
             } else {
 #pragma unroll 4
-                for (int k = 0; k < BLOCK; ++k) interact_local<R, SAFE, false>(L, ftile[k], rx, ry, rz, P.sc.eps2f);
+                for (int k = 0; k < BLOCK; ++k) interact_local<R, SAFE, false>(L, ftile[k], rx, ry, rz, eps2f);
             }
             flush(L, um, (double)m0);
         } else {
@@ -683,28 +691,91 @@ __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk)
 #pragma unroll 4
                 for (int k = 0; k < BLOCK; ++k) {
                     const JM &f = dtile[k];
-                    interact<P_MIXED, R, MODE_ACC, SAFE, true>(L, f.x, f.y, f.z, 0, 0, 0, 0, 0, P.sc.eps2,
-                                                                P.sc.eps2f);
+                    interact<P_MIXED, R, MODE_ACC, SAFE, true>(L, f.x, f.y, f.z, 0, 0, 0, 0, 0, eps2, eps2f);
                 }
             } else {
 #pragma unroll 4
-                for (int k = 0; k < BLOCK; ++k) interact_src<P_MIXED, R, MODE_ACC, SAFE>(L, dtile[k], P.sc.eps2, P.sc.eps2f);
+                for (int k = 0; k < BLOCK; ++k) interact_src<P_MIXED, R, MODE_ACC, SAFE>(L, dtile[k], eps2, eps2f);
             }
             flush(L, um, m0);
         }
         __syncthreads();
     }
+}
+
+template <int R, bool SAFE, bool EXP>
+__global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk) {
+    constexpr int BLOCK = 256;
+    __shared__ JL ftile[BLOCK];
+    __shared__ JM dtile[BLOCK];
+    __shared__ float fmass[EXP ? BLOCK : 1];
+    const int64_t n = P.sc.n;
+    const LocalSys O{P.lo.px, P.lo.py, P.lo.pz, P.lo.pm, P.lo.tbox, n};
+    // targets: sorted positions [i0, i1), in the workgroup tiles of a launch
+    // over all n (so a range gives the full launch's bits)
+    const int64_t ib = (P.i0 / (BLOCK * R) + (int64_t)blockIdx.x) * (BLOCK * R);
+    const int64_t jb = (int64_t)blockIdx.y * chunk;
+    const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+    const int t = threadIdx.x;
+    Lane<P_MIXED, R> L;
+    lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, BLOCK);
+    local_sweep<R, SAFE, EXP>(L, O, ib, jb, je, P.sc.eps2, P.sc.eps2f, ftile, dtile, fmass);
+    const int64_t rows = P.i1 - P.i0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = ib + (int64_t)r * BLOCK + t;
-        if (i >= n) continue;
+        if (i < P.i0 || i >= P.i1) continue;
         double sx, sy, sz, sp;
         raw<P_MIXED, R>(L, r, sx, sy, sz, sp);
         if (P.split > 1) {
-            double *q = P.part + (int64_t)blockIdx.y * 4 * n + i;
-            q[0] = sx; q[n] = sy; q[2 * n] = sz; q[3 * n] = sp;
+            double *q = P.part + (int64_t)blockIdx.y * 4 * rows + (i - P.i0);
+            q[0] = sx; q[rows] = sy; q[2 * rows] = sz; q[3 * rows] = sp;
         } else {
-            finish<P_MIXED, MODE_ACC>(P.st, P.sc, O.perm[i], sx, sy, sz, sp, P.kick, P.hdt);
+            finish<P_MIXED, MODE_ACC>(P.st, P.sc, P.lo.perm[i], sx, sy, sz, sp, P.kick, P.hdt);
+        }
+    }
+}
+
+// Batched form: a persistent grid walks work items (system, tile of R * 256
+// sorted targets, source chunk) of the systems taken in spatial order; each
+// item does what the single-system kernel's workgroup (blockIdx.x, chunk)
+// does for that system, so a system's sums are bitwise those of a single
+// launch with the same R, split and far-tile form.
+template <int R, bool EXP>
+__global__ __launch_bounds__(256) void k_pair_local_batched(BatchLaunch B) {
+    constexpr int BLOCK = 256;
+    __shared__ JL ftile[BLOCK];
+    __shared__ JM dtile[BLOCK];
+    __shared__ float fmass[EXP ? BLOCK : 1];
+    const int t = threadIdx.x;
+    for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
+        const WorkItem it = B.items[w];
+        const SysConst sc = B.sys[it.sys];
+        const BatchSys ly = B.lay[it.sys];
+        const int64_t n = sc.n, off = sc.off;
+        const LocalSys O{B.lo.px + off, B.lo.py + off, B.lo.pz + off, B.lo.pm + off, B.lo.tbox + 6 * ly.tbase, n};
+        const int64_t ib = it.i0;
+        const int64_t jb = (int64_t)it.chunk * ly.chunk;
+        const int64_t je = (jb + ly.chunk < n) ? jb + ly.chunk : n;
+        Lane<P_MIXED, R> L;
+        lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, BLOCK);
+        if (sc.safe32)
+            local_sweep<R, true, EXP>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile, fmass);
+        else
+            local_sweep<R, false, EXP>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile, fmass);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = ib + (int64_t)r * BLOCK + t;
+            if (i >= n) continue;
+            double sx, sy, sz, sp;
+            raw<P_MIXED, R>(L, r, sx, sy, sz, sp);
+            if (ly.split > 1) {
+                double *q = B.part + ly.pbase + (int64_t)it.chunk * 4 * n + i;
+                q[0] = sx; q[n] = sy; q[2 * n] = sz; q[3 * n] = sp;
+            } else {
+                finish<P_MIXED, MODE_ACC>(B.st, sc, B.lo.perm[off + i], sx, sy, sz, sp, B.kick_scale != 0.0,
+                                          0.5 * B.kick_scale * sc.dt);
+            }
         }
     }
 }
@@ -713,7 +784,7 @@ template <int R, bool EXP>
 hipError_t go_local(const PairLaunch &P, hipStream_t s) {
     const int64_t n = P.sc.n;
     const int64_t per = 256LL * R;
-    const int64_t nbx = (n + per - 1) / per;
+    const int64_t nbx = (P.i1 - (P.i0 / per) * per + per - 1) / per;
     const int64_t per_chunk = (n + P.split - 1) / P.split;
     const int64_t chunk = ((per_chunk + 255) / 256) * 256;
     if (nbx <= 0) return hipSuccess;
@@ -726,8 +797,8 @@ hipError_t go_local(const PairLaunch &P, hipStream_t s) {
 }
 
 hipError_t pick_local(const PairLaunch &P, hipStream_t s) {
-    if (P.sc.prec != P_MIXED || P.mode != MODE_ACC || P.block != 256 || P.i0 != 0 || P.i1 != P.sc.n ||
-        !P.lo.perm)
+    if (P.sc.prec != P_MIXED || P.mode != MODE_ACC || P.block != 256 || P.i0 < 0 || P.i1 > P.sc.n ||
+        P.i1 <= P.i0 || !P.lo.perm)
         return hipErrorInvalidValue;
     const bool exp = P.jsrc == 3;
     if (P.R == 1) return exp ? go_local<1, true>(P, s) : go_local<1, false>(P, s);
@@ -746,23 +817,70 @@ __global__ __launch_bounds__(BLOCK) void k_pair_batched(BatchLaunch B) {
         const WorkItem it = B.items[w];
         const SysConst sc = B.sys[it.sys];
         const int64_t ilim = sc.off + sc.n;
+        const int64_t ib = sc.off + it.i0;
+        // the item's source chunk (without a layout table: the whole system)
+        int64_t jb = sc.off, je = ilim;
+        int32_t split = 1;
+        int64_t pbase = 0;
+        if (B.lay) {
+            const BatchSys ly = B.lay[it.sys];
+            split = ly.split;
+            pbase = ly.pbase;
+            jb = sc.off + (int64_t)it.chunk * ly.chunk;
+            je = (jb + ly.chunk < ilim) ? jb + ly.chunk : ilim;
+        }
         Lane<PREC, R> L;
-        lane_init<PREC, R>(L, B.st, it.i0, ilim, BLOCK);
+        lane_init<PREC, R>(L, B.st, ib, ilim, BLOCK);
         const bool safe = (PREC == P_FP64) ? sc.safe64 : sc.safe32;
         if (safe)
-            sweep_lds<PREC, R, BLOCK, MODE, true>(L, B.st, sc.off, ilim, it.i0, sc.eps2, sc.eps2f, tile);
+            sweep_lds<PREC, R, BLOCK, MODE, true>(L, B.st, jb, je, ib, sc.eps2, sc.eps2f, tile);
         else
-            sweep_lds<PREC, R, BLOCK, MODE, false>(L, B.st, sc.off, ilim, it.i0, sc.eps2, sc.eps2f, tile);
+            sweep_lds<PREC, R, BLOCK, MODE, false>(L, B.st, jb, je, ib, sc.eps2, sc.eps2f, tile);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t i = it.i0 + (int64_t)r * BLOCK + threadIdx.x;
+            const int64_t i = ib + (int64_t)r * BLOCK + threadIdx.x;
             if (i >= ilim) continue;
             double sx, sy, sz, sp;
             raw<PREC, R>(L, r, sx, sy, sz, sp);
-            finish<PREC, MODE>(B.st, sc, i, sx, sy, sz, sp, B.kick_scale != 0.0,
-                               0.5 * B.kick_scale * sc.dt);
+            if (split > 1) {
+                const int64_t n = sc.n;
+                double *q = B.part + pbase + (int64_t)it.chunk * 4 * n + (i - sc.off);
+                q[0] = sx; q[n] = sy; q[2 * n] = sz; q[3 * n] = sp;
+            } else {
+                finish<PREC, MODE>(B.st, sc, i, sx, sy, sz, sp, B.kick_scale != 0.0, 0.5 * B.kick_scale * sc.dt);
+            }
         }
     }
+}
+
+// Fixed-order reduction of the batched split partial sums (acceleration
+// only; float32 systems never split): one lane per particle of a system with
+// split > 1, summing its chunks in order as k_pair_reduce does.
+__global__ __launch_bounds__(256) void k_pair_reduce_batched(BatchLaunch B, const int64_t *off, int32_t nsys,
+                                                             int64_t ntot) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= ntot) return;
+    int32_t lo = 0, hi = nsys;  // system of p: largest b with off[b] <= p
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= p) lo = mid; else hi = mid;
+    }
+    const BatchSys ly = B.lay[lo];
+    if (ly.split <= 1) return;
+    const SysConst sc = B.sys[lo];
+    const int64_t n = sc.n, q = p - sc.off;
+    const double *b = B.part + ly.pbase + q;
+    double sx = 0, sy = 0, sz = 0, sp = 0;
+    for (int s = 0; s < ly.split; ++s) {
+        const double *c = b + (int64_t)s * 4 * n;
+        sx += c[0]; sy += c[n]; sz += c[2 * n]; sp += c[3 * n];
+    }
+    // rows are sorted positions for a system summed in spatial order
+    const int64_t i = ly.local ? (int64_t)B.lo.perm[p] : p;
+    const int kick = B.kick_scale != 0.0;
+    const double hdt = 0.5 * B.kick_scale * sc.dt;
+    if (sc.prec == P_FP64) finish<P_FP64, MODE_ACC>(B.st, sc, i, sx, sy, sz, sp, kick, hdt);
+    else finish<P_MIXED, MODE_ACC>(B.st, sc, i, sx, sy, sz, sp, kick, hdt);
 }
 
 // ---------------------------------------------------------------------------
@@ -858,6 +976,21 @@ hipError_t batched_prec(const BatchLaunch &B, hipStream_t s) {
     }
 }
 
+template <int R, bool EXP>
+hipError_t go_local_batched(const BatchLaunch &B, hipStream_t s) {
+    if (B.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pair_local_batched<R, EXP>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+template <int R, bool EXP>
+int occ_local() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_local_batched<R, EXP>, 256, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
 template <int PREC, int R, int MODE>
 int occ_of() {
     int nb = 0;
@@ -873,6 +1006,27 @@ int occ_prec(int R, int mode) {
 }
 
 }  // namespace
+
+int pair_local_batched_occupancy(int R, int jsrc) {
+    if (R == 2) return jsrc == 3 ? occ_local<2, true>() : occ_local<2, false>();
+    return jsrc == 3 ? occ_local<1, true>() : occ_local<1, false>();
+}
+
+hipError_t launch_pair_local_batched(const BatchLaunch &B, int jsrc, hipStream_t s) {
+    if (B.block != 256 || B.mode != MODE_ACC || B.prec != P_MIXED || !B.lay || !B.lo.perm) return hipErrorInvalidValue;
+    if (jsrc != 2 && jsrc != 3) return hipErrorInvalidValue;
+    if (B.R == 1) return jsrc == 3 ? go_local_batched<1, true>(B, s) : go_local_batched<1, false>(B, s);
+    if (B.R == 2) return jsrc == 3 ? go_local_batched<2, true>(B, s) : go_local_batched<2, false>(B, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pair_reduce_batched(const BatchLaunch &B, const int64_t *off, int32_t nsys, int64_t ntot,
+                                      hipStream_t s) {
+    if (ntot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_reduce_batched, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, B, off, nsys,
+                       ntot);
+    return hipGetLastError();
+}
 
 int pair_batched_occupancy(int prec, int R, int block, int mode) {
     (void)block;

@@ -2,10 +2,13 @@
 //   K = sum m |v|^2 / 2,  W = (1/2) sum m_i phi_i  (phi from the float64
 //   potential pass of accel.hip, self pair excluded),  Wext = sum m Phi_h,
 //   P = sum m v,  L = sum m r x v,  com = sum m r / M,  M = sum m.
-// One workgroup per system: each lane sums a fixed strided subset, lanes are
-// combined by a fixed xor-butterfly inside each wave (DPP / ds_swizzle
-// shuffles) and the four wave sums in wave order, so the result is
-// bitwise reproducible for a given n.  Always float64.
+// Two passes in a fixed order, so the result is bitwise reproducible for a
+// given n: every segment of kSeg particles of a system is reduced by one
+// workgroup (each lane a fixed strided subset, lanes combined by a fixed
+// xor-butterfly inside each wave and the four wave sums in wave order), then
+// one workgroup per system reduces its segments' sums the same way.  The
+// first pass spreads an HBM-bound O(N) read over many workgroups.  Always
+// float64.
 #include <algorithm>
 
 #include "nbody_internal.h"
@@ -23,14 +26,48 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_diag(State st, const double *phi, const SysConst *sys,
-                                                   double *out) {
-    const SysConst sc = sys[blockIdx.x];
+constexpr int64_t kSeg = 2048;  // particles per first-pass segment
+
+// Sum over the workgroup of q[0..kQ) (lane 0 holds the result).
+__device__ __forceinline__ void block_sum(double *q) {
+    __shared__ double part[kThreads / 64][kQ];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        const double v = wave_sum(q[k]);
+        if (lane == 0) part[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kQ; ++k) {
+            double t = part[0][k];
+            for (int w = 1; w < kThreads / 64; ++w) t += part[w][k];
+            q[k] = t;
+        }
+    }
+}
+
+// Segment g: system b = segment_of(segbase, g) (single system: segbase NULL,
+// b = 0), particles [off + (g - segbase[b]) kSeg, +kSeg) of it.
+__global__ __launch_bounds__(kThreads) void k_diag_seg(State st, const double *phi, const SysConst *sys,
+                                                       const int64_t *segbase, int32_t B, double *parts) {
+    const int64_t g = blockIdx.x;
+    int32_t b = 0;
+    if (segbase) {
+        int32_t lo = 0, hi = B;  // largest b with segbase[b] <= g
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (segbase[mid] <= g) lo = mid; else hi = mid;
+        }
+        b = lo;
+    }
+    const SysConst sc = sys[b];
+    const int64_t first = sc.off + (g - (segbase ? segbase[b] : 0)) * kSeg;
+    const int64_t e = std::min<int64_t>(sc.off + sc.n, first + kSeg);
     double q[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; ++k) q[k] = 0.0;
-    const int64_t e = sc.off + sc.n;
-    for (int64_t i = sc.off + threadIdx.x; i < e; i += kThreads) {
+    for (int64_t i = first + threadIdx.x; i < e; i += kThreads) {
         const double m = st.m[i];
         const double x = st.x[i], y = st.y[i], z = st.z[i];
         const double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
@@ -44,26 +81,37 @@ __global__ __launch_bounds__(kThreads) void k_diag(State st, const double *phi, 
         q[9] += m * x; q[10] += m * y; q[11] += m * z;
         q[12] += m;
     }
-    __shared__ double part[kThreads / 64][kQ];
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-#pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-        const double v = wave_sum(q[k]);
-        if (lane == 0) part[wave][k] = v;
-    }
-    __syncthreads();
+    block_sum(q);
     if (threadIdx.x == 0) {
-        double t[kQ];
-        for (int k = 0; k < kQ; ++k) {
-            t[k] = part[0][k];
-            for (int w = 1; w < kThreads / 64; ++w) t[k] += part[w][k];
-        }
-        double *o = out + (int64_t)blockIdx.x * 14;
-        const double M = t[12];
-        o[0] = t[0]; o[1] = t[1]; o[2] = t[2]; o[3] = t[0] + t[1] + t[2];
-        o[4] = t[3]; o[5] = t[4]; o[6] = t[5];
-        o[7] = t[6]; o[8] = t[7]; o[9] = t[8];
-        o[10] = M > 0 ? t[9] / M : 0.0; o[11] = M > 0 ? t[10] / M : 0.0; o[12] = M > 0 ? t[11] / M : 0.0;
+        double *o = parts + g * kQ;
+        for (int k = 0; k < kQ; ++k) o[k] = q[k];
+    }
+}
+
+// One workgroup per system: its segments' sums in a fixed order, then the
+// 14 outputs.
+__global__ __launch_bounds__(kThreads) void k_diag_final(const SysConst *sys, const int64_t *segbase,
+                                                         const double *parts, double *out) {
+    const int32_t b = blockIdx.x;
+    const SysConst sc = sys[b];
+    const int64_t g0 = segbase ? segbase[b] : 0;
+    const int64_t ns = (sc.n + kSeg - 1) / kSeg;
+    double q[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) q[k] = 0.0;
+    for (int64_t g = threadIdx.x; g < ns; g += kThreads) {
+        const double *p = parts + (g0 + g) * kQ;
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) q[k] += p[k];
+    }
+    block_sum(q);
+    if (threadIdx.x == 0) {
+        double *o = out + (int64_t)b * 14;
+        const double M = q[12];
+        o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[0] + q[1] + q[2];
+        o[4] = q[3]; o[5] = q[4]; o[6] = q[5];
+        o[7] = q[6]; o[8] = q[7]; o[9] = q[8];
+        o[10] = M > 0 ? q[9] / M : 0.0; o[11] = M > 0 ? q[10] / M : 0.0; o[12] = M > 0 ? q[11] / M : 0.0;
         o[13] = M;
     }
 }
@@ -103,10 +151,13 @@ hipError_t launch_surface_density(const double *x, const double *y, int64_t n, i
     return hipGetLastError();
 }
 
+int64_t diag_segments(int64_t n) { return (n + kSeg - 1) / kSeg; }
+
 hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst *sys, int32_t B,
-                              double *out, hipStream_t s) {
+                              const int64_t *segbase, int64_t nseg, double *parts, double *out, hipStream_t s) {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag, dim3((unsigned)B), dim3(kThreads), 0, s, st, phi, sys, out);
+    if (nseg > 0) hipLaunchKernelGGL(k_diag_seg, dim3((unsigned)nseg), dim3(kThreads), 0, s, st, phi, sys, segbase, B, parts);
+    hipLaunchKernelGGL(k_diag_final, dim3((unsigned)B), dim3(kThreads), 0, s, sys, segbase, (const double *)parts, out);
     return hipGetLastError();
 }
 

@@ -56,14 +56,27 @@ struct PairLaunch {
     double hdt;        // > 0 (or != 0): fuse the closing half kick v += hdt a
     int32_t kick;
     double *part;      // split > 1: [split][4][i1 - i0] partial sums
-    LocalOrder lo;     // jsrc = 2 only; rows are then sorted positions
+    LocalOrder lo;     // jsrc = 2 and 3: rows [i0, i1) are then sorted positions
 };
 
-// One work item of a batched launch: a tile of targets of one system.
+// One work item of a batched launch: a tile of targets of one system
+// against one chunk of its sources.
 struct WorkItem {
     int32_t sys;
-    int32_t pad;
-    int64_t i0;        // first target (global index) of the tile
+    int32_t chunk;     // source chunk (0 .. split - 1 of the system)
+    int64_t i0;        // first target of the tile, relative to the system's first
+                       // particle (sorted position for systems in spatial order)
+};
+
+// Per-system layout of a batched launch (device table, one per system).  A
+// system's sources are cut into `split` chunks of `chunk` particles (a
+// multiple of 256; the same chunks as a single launch with that split).
+struct BatchSys {
+    int64_t chunk;
+    int64_t tbase;     // first tile of the system in the batch's tile-box table
+    int64_t pbase;     // first double of its split partial sums ([split][4][n])
+    int32_t split;     // 1: the items finish the sums themselves
+    int32_t local;     // 1: summed in spatial order
 };
 
 struct BatchLaunch {
@@ -74,12 +87,21 @@ struct BatchLaunch {
     int32_t prec, mode, R, block;
     int32_t grid;             // persistent workgroups
     double kick_scale;        // closing half kick v += kick_scale * dt_sys * a (0: none)
+    const BatchSys *lay;      // device, one per system (NULL: whole systems, no split)
+    double *part;             // split partial sums of all systems
+    LocalOrder lo;            // the batch's spatial order (systems summed in it)
 };
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_pair(const PairLaunch &L, hipStream_t s);
 hipError_t launch_pair_reduce(const PairLaunch &L, hipStream_t s);
 hipError_t launch_pair_batched(const BatchLaunch &L, hipStream_t s);
+// mixed systems in spatial order (jsrc 2 or 3), items over sorted positions
+hipError_t launch_pair_local_batched(const BatchLaunch &L, int jsrc, hipStream_t s);
+int pair_local_batched_occupancy(int R, int jsrc);
+// fixed-order reduction of the split partial sums of every system with split > 1
+hipError_t launch_pair_reduce_batched(const BatchLaunch &L, const int64_t *off, int32_t nsys, int64_t ntot,
+                                      hipStream_t s);
 bool pair_config_supported(int prec, int R, int block, int jsrc, int mode);
 // resident workgroups per CU of the batched kernel for (prec, R, block, mode)
 int pair_batched_occupancy(int prec, int R, int block, int mode);
@@ -96,10 +118,15 @@ hipError_t launch_kick_drift_batched(const State &st, const int64_t *off_dev,
 hipError_t launch_kick_batched(const State &st, const int64_t *off_dev, const SysConst *sys,
                                int32_t B, int64_t ntot, double w, hipStream_t s);
 
-// Diagnostics: one workgroup per system reduces K, W (from phi), Wext, P, L,
-// centre of mass and M in a fixed order and writes 14 doubles per system.
-hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst *sys,
-                              int32_t B, double *out, hipStream_t s);
+// Diagnostics: K, W (from phi), Wext, P, L, centre of mass and M of each of
+// B systems in a fixed order, 14 doubles per system.  First pass: one
+// workgroup per segment of diag_segments(n) of each system (segbase: B + 1
+// device offsets of each system's first segment, NULL for a single system;
+// nseg segments in all) into parts (13 doubles per segment); second pass:
+// one workgroup per system.
+int64_t diag_segments(int64_t n);
+hipError_t launch_diag_reduce(const State &st, const double *phi, const SysConst *sys, int32_t B,
+                              const int64_t *segbase, int64_t nseg, double *parts, double *out, hipStream_t s);
 
 // Acceleration and jerk pair sum (fourth-order Hermite).  The sum is
 // evaluated at (x, v); without corr it stores a and j, with corr it applies
@@ -140,6 +167,14 @@ size_t local_order_bytes(int64_t n);
 hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOrder *out, hipStream_t s);
 // the sorted Morton keys inside that scratch (valid after launch_local_order)
 const uint64_t *local_order_keys(const void *scratch, int64_t n);
+// The spatial orders of all B systems of a batch at once: each system's
+// particles sorted as launch_local_order sorts that system alone (its own
+// box and keys; systems stay in order), perm holding global indices, and the
+// tile boxes of each system (tiles of 256 from its first particle) from
+// tbase[b] on (tbase: B + 1 device entries, ntiles = tbase[B]).
+size_t batch_order_bytes(int64_t ntot, int64_t ntiles, int32_t B);
+hipError_t launch_batch_order(const State &st, const int64_t *off, const int64_t *tbase, int32_t B, int64_t ntot,
+                              int64_t ntiles, void *scratch, LocalOrder *out, hipStream_t s);
 hipError_t launch_hermite_predict(const HermitePredict &H, int fp32, hipStream_t s);
 hipError_t launch_rk4(const RK4Launch &K, int fp32, hipStream_t s);
 hipError_t launch_surface_density(const double *x, const double *y, int64_t n, int32_t nx, int32_t ny,

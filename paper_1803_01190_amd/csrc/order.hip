@@ -112,21 +112,48 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
     return v;
 }
 
-__global__ __launch_bounds__(kT) void k_morton(State st, int64_t n, const double *box, uint64_t *key) {
-    // one cubic grid of 2^21 cells per side over the system's box
+// Key of particle i on one cubic grid of 2^21 cells per side over its
+// system's box.
+__device__ __forceinline__ uint64_t morton_key(const State &st, int64_t i, const double *box) {
     const double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
     const double scale = ext > 0.0 ? 2097151.0 / ext : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-        const double p[3] = {st.x[i], st.y[i], st.z[i]};
-        uint64_t k = 0;
+    const double p[3] = {st.x[i], st.y[i], st.z[i]};
+    uint64_t k = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double q = (p[c] - box[c]) * scale;
-            q = fmin(fmax(q, 0.0), 2097151.0);  // NaN becomes 0
-            k |= spread3((uint64_t)q) << c;
-        }
-        key[i] = k;
+    for (int c = 0; c < 3; ++c) {
+        double q = (p[c] - box[c]) * scale;
+        q = fmin(fmax(q, 0.0), 2097151.0);  // NaN becomes 0
+        k |= spread3((uint64_t)q) << c;
     }
+    return k;
+}
+
+__global__ __launch_bounds__(kT) void k_morton(State st, int64_t n, const double *box, uint64_t *key) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+        key[i] = morton_key(st, i, box);
+}
+
+// Index of the segment holding i: the largest b with seg[b] <= i (seg has
+// nseg + 1 non-decreasing entries, seg[0] <= i < seg[nseg]).
+__device__ __forceinline__ int32_t segment_of(const int64_t *seg, int32_t nseg, int64_t i) {
+    int32_t lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (seg[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Batches: one workgroup per system for its box; keys on each system's box.
+__global__ __launch_bounds__(kT) void k_sys_box(State st, const int64_t *off, double *boxes) {
+    const int b = blockIdx.x;
+    block_box(st.x, st.y, st.z, off[b], off[b + 1], kT, boxes + 6 * (int64_t)b);
+}
+
+__global__ __launch_bounds__(kT) void k_morton_batched(State st, const int64_t *off, int32_t B, int64_t n,
+                                                       const double *boxes, uint64_t *key) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+        key[i] = morton_key(st, i, boxes + 6 * (int64_t)segment_of(off, B, i));
 }
 
 // ---- stable radix sort of (key, index) ------------------------------------
@@ -137,14 +164,28 @@ __global__ __launch_bounds__(kT) void k_morton(State st, int64_t n, const double
 // their positions (ranks inside a tile from wave ballots), which keeps equal
 // digits in input order.
 
-__global__ __launch_bounds__(kT) void k_sort_hist(const uint64_t *key, int64_t n, int shift, int64_t per, int nb,
-                                                  uint32_t *hist) {
+// The sort digit of an element: 8 bits of its key, or, in the passes that
+// order a batch by system (seg != NULL), 8 bits of the index of the system
+// that holds the element's particle.
+struct Digit {
+    const int64_t *seg;
+    int32_t nseg;
+    int32_t shift;
+    __device__ __forceinline__ uint32_t operator()(uint64_t key, int32_t id) const {
+        const uint64_t v = seg ? (uint64_t)segment_of(seg, nseg, id) : key;
+        return (uint32_t)(v >> shift) & 0xffu;
+    }
+};
+
+__global__ __launch_bounds__(kT) void k_sort_hist(const uint64_t *key, const int32_t *iin, int64_t n, Digit dg,
+                                                  int64_t per, int nb, uint32_t *hist) {
     __shared__ uint32_t cnt[kBins];
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t b0 = (int64_t)blockIdx.x * per * kT;
     const int64_t e = std::min<int64_t>(n, b0 + per * kT);
-    for (int64_t i = b0 + threadIdx.x; i < e; i += kT) atomicAdd(&cnt[(uint32_t)(key[i] >> shift) & 0xffu], 1u);
+    for (int64_t i = b0 + threadIdx.x; i < e; i += kT)
+        atomicAdd(&cnt[dg(key[i], iin ? iin[i] : (int32_t)i)], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
@@ -195,7 +236,7 @@ __global__ __launch_bounds__(kT) void k_sort_scan(uint32_t *hist, int nb, uint32
 }
 
 __global__ __launch_bounds__(kT) void k_sort_scatter(const uint64_t *kin, const int32_t *iin, uint64_t *kout,
-                                                     int32_t *iout, int64_t n, int shift, int64_t per, int nb,
+                                                     int32_t *iout, int64_t n, Digit dg, int64_t per, int nb,
                                                      const uint32_t *hist, const uint32_t *tot) {
     __shared__ uint32_t run[kBins];
     __shared__ uint32_t cnt[kT / 64][kBins];
@@ -213,7 +254,7 @@ __global__ __launch_bounds__(kT) void k_sort_scatter(const uint64_t *kin, const 
         const bool ok = i < e;
         const uint64_t k = ok ? kin[i] : 0ull;
         const int32_t id = ok ? (iin ? iin[i] : (int32_t)i) : 0;
-        const uint32_t d = (uint32_t)(k >> shift) & 0xffu;
+        const uint32_t d = dg(k, id);
         // lanes of this wave holding a valid key with the same digit
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -264,6 +305,17 @@ __global__ __launch_bounds__(kT) void k_tile_box(const double *px, const double 
     block_box(px, py, pz, b, std::min<int64_t>(n, b + kT), kT, tbox + 6 * (int64_t)blockIdx.x);
 }
 
+// Batches: tile g is tile k = g - tbase[b] of system b (tiles of 256 sorted
+// particles counted from the system's first).
+__global__ __launch_bounds__(kT) void k_tile_box_batched(const double *px, const double *py, const double *pz,
+                                                         const int64_t *off, const int64_t *tbase, int32_t B,
+                                                         double *tbox) {
+    const int64_t g = blockIdx.x;
+    const int32_t b = segment_of(tbase, B, g);
+    const int64_t lo = off[b] + (g - tbase[b]) * kT;
+    block_box(px, py, pz, lo, std::min<int64_t>(off[b + 1], lo + kT), kT, tbox + 6 * g);
+}
+
 inline unsigned grid_for(int64_t n) {
     const int64_t g = (n + kT - 1) / kT;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
@@ -282,17 +334,17 @@ SortShape sort_shape(int64_t n) {
     return {(int)((tiles + per - 1) / per), per};
 }
 
-// Byte offsets of the pieces of the order scratch.  The sort ping-pongs
-// between (key_a, idx_a) and (key_b, idx_b); after its even number of
-// passes the sorted keys and the permutation are in key_a and idx_a.
+// Byte offsets of the pieces of the order scratch for n particles in
+// `tiles` tiles and nsys systems (box: one per system).  The sort ping-pongs
+// between (key_a, idx_a) and (key_b, idx_b).
 struct Layout {
     size_t key_a, key_b, idx_a, idx_b, px, py, pz, pm, tbox, parts, box, hist, tot, total;
 };
 
-Layout layout(int64_t n) {
+Layout layout(int64_t n, int64_t tiles_in, int32_t nsys) {
     Layout L{};
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
-    const size_t tiles = (nn + kT - 1) / kT;
+    const size_t tiles = (size_t)std::max<int64_t>(tiles_in, 1);
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
     L.key_a = take(8 * nn);
@@ -305,16 +357,48 @@ Layout layout(int64_t n) {
     L.pm = take(8 * nn);
     L.tbox = take(48 * tiles);
     L.parts = take(48 * kParts);
-    L.box = take(48);
+    L.box = take(48 * (size_t)std::max(nsys, 1));
     L.hist = take(4 * (size_t)kBins * sort_shape(n).nb);
     L.tot = take(4 * kBins);
     L.total = o;
     return L;
 }
 
+Layout layout(int64_t n) { return layout(n, (n + kT - 1) / kT, 1); }
+
+// Passes over the system index that follow the key passes of a batch.
+int system_passes(int32_t B) {
+    int p = 0;
+    for (uint32_t v = (uint32_t)std::max(B - 1, 0); v > 0; v >>= 8) ++p;
+    return p;
+}
+
+// Stable radix sort of the keys in key_a (index payload: the identity) by
+// their 8 key bytes and then, for a batch, by the bytes of their system
+// index.  Returns whether the result landed in the second buffers.
+bool sort_pairs(uint64_t *key_a, uint64_t *key_b, int32_t *idx_a, int32_t *idx_b, int64_t n, const int64_t *off,
+                int32_t B, uint32_t *hist, uint32_t *tot, hipStream_t s) {
+    const SortShape S = sort_shape(n);
+    const int passes = kPasses + (off ? system_passes(B) : 0);
+    for (int p = 0; p < passes; ++p) {
+        const bool even = (p % 2) == 0;
+        const uint64_t *kin = even ? key_a : key_b;
+        uint64_t *kout = even ? key_b : key_a;
+        const int32_t *iin = p == 0 ? nullptr : (even ? idx_a : idx_b);  // first pass: identity
+        int32_t *iout = even ? idx_b : idx_a;
+        Digit dg{nullptr, 0, 8 * p};
+        if (p >= kPasses) dg = Digit{off, B, 8 * (p - kPasses)};
+        hipLaunchKernelGGL(k_sort_hist, dim3(S.nb), dim3(kT), 0, s, kin, iin, n, dg, S.per, S.nb, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kBins), dim3(kT), 0, s, hist, S.nb, tot);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(S.nb), dim3(kT), 0, s, kin, iin, kout, iout, n, dg, S.per, S.nb,
+                           (const uint32_t *)hist, (const uint32_t *)tot);
+    }
+    return passes % 2 == 1;
+}
+
 }  // namespace
 
-static_assert(kPasses % 2 == 0, "the sorted keys must end in the first buffer");
+static_assert(kPasses % 2 == 0, "a single system's sorted keys end in the first buffer");
 
 size_t local_order_bytes(int64_t n) { return layout(n).total; }
 
@@ -325,7 +409,6 @@ const uint64_t *local_order_keys(const void *scratch, int64_t n) {
 hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOrder *out, hipStream_t s) {
     if (n <= 0 || n > INT32_MAX) return hipErrorInvalidValue;
     const Layout L = layout(n);
-    const SortShape S = sort_shape(n);
     char *base = (char *)scratch;
     uint64_t *key_a = (uint64_t *)(base + L.key_a), *key_b = (uint64_t *)(base + L.key_b);
     int32_t *idx_a = (int32_t *)(base + L.idx_a), *idx_b = (int32_t *)(base + L.idx_b);
@@ -336,24 +419,41 @@ hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOr
     hipLaunchKernelGGL(k_box_partial, dim3(kParts), dim3(kT), 0, s, st, n, parts);
     hipLaunchKernelGGL(k_box_final, dim3(1), dim3(kT), 0, s, parts, kParts, box);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kT), 0, s, st, n, box, key_a);
-    for (int p = 0; p < kPasses; ++p) {
-        const int shift = 8 * p;
-        const bool even = (p % 2) == 0;
-        const uint64_t *kin = even ? key_a : key_b;
-        uint64_t *kout = even ? key_b : key_a;
-        const int32_t *iin = p == 0 ? nullptr : (even ? idx_a : idx_b);  // first pass: identity
-        int32_t *iout = even ? idx_b : idx_a;
-        hipLaunchKernelGGL(k_sort_hist, dim3(S.nb), dim3(kT), 0, s, kin, n, shift, S.per, S.nb, hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(kBins), dim3(kT), 0, s, hist, S.nb, tot);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(S.nb), dim3(kT), 0, s, kin, iin, kout, iout, n, shift, S.per, S.nb,
-                           (const uint32_t *)hist, (const uint32_t *)tot);
-    }
+    (void)sort_pairs(key_a, key_b, idx_a, idx_b, n, nullptr, 1, hist, tot, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int32_t *perm = idx_a;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kT), 0, s, st, n, perm, px, py, pz, pm);
     const int64_t tiles = (n + kT - 1) / kT;
     hipLaunchKernelGGL(k_tile_box, dim3((unsigned)tiles), dim3(kT), 0, s, px, py, pz, n, tbox);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    out->perm = perm;
+    out->px = px; out->py = py; out->pz = pz; out->pm = pm;
+    out->tbox = tbox;
+    return hipSuccess;
+}
+
+size_t batch_order_bytes(int64_t ntot, int64_t ntiles, int32_t B) { return layout(ntot, ntiles, B).total; }
+
+hipError_t launch_batch_order(const State &st, const int64_t *off, const int64_t *tbase, int32_t B, int64_t ntot,
+                              int64_t ntiles, void *scratch, LocalOrder *out, hipStream_t s) {
+    if (ntot <= 0 || ntot > INT32_MAX || B < 1 || ntiles < 1) return hipErrorInvalidValue;
+    const Layout L = layout(ntot, ntiles, B);
+    char *base = (char *)scratch;
+    uint64_t *key_a = (uint64_t *)(base + L.key_a), *key_b = (uint64_t *)(base + L.key_b);
+    int32_t *idx_a = (int32_t *)(base + L.idx_a), *idx_b = (int32_t *)(base + L.idx_b);
+    double *px = (double *)(base + L.px), *py = (double *)(base + L.py), *pz = (double *)(base + L.pz);
+    double *pm = (double *)(base + L.pm), *tbox = (double *)(base + L.tbox), *boxes = (double *)(base + L.box);
+    uint32_t *hist = (uint32_t *)(base + L.hist), *tot = (uint32_t *)(base + L.tot);
+    hipLaunchKernelGGL(k_sys_box, dim3((unsigned)B), dim3(kT), 0, s, st, off, boxes);
+    hipLaunchKernelGGL(k_morton_batched, dim3(grid_for(ntot)), dim3(kT), 0, s, st, off, B, ntot, boxes, key_a);
+    const bool in_b = sort_pairs(key_a, key_b, idx_a, idx_b, ntot, off, B, hist, tot, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int32_t *perm = in_b ? idx_b : idx_a;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kT), 0, s, st, ntot, perm, px, py, pz, pm);
+    hipLaunchKernelGGL(k_tile_box_batched, dim3((unsigned)ntiles), dim3(kT), 0, s, px, py, pz, off, tbase, B, tbox);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     out->perm = perm;

@@ -44,6 +44,8 @@ struct nbody_ctx {
     size_t order_cap = 0;     // doubles
     double *jvel = nullptr;   // velocities in that order (jerk plans with jsrc 2)
     size_t jvel_cap = 0;      // doubles
+    double *dseg = nullptr;   // per-segment sums of the diagnostics' first pass
+    size_t dseg_cap = 0;      // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
     // Scratch outgrown by a larger call is kept (not freed) until the
     // context is destroyed: a HIP graph captured earlier may still use it,
@@ -66,16 +68,38 @@ struct nbody_batch {
     std::vector<SysConst> sc;
     int64_t *off_dev = nullptr;
     SysConst *sc_dev = nullptr;
-    int R = 2, block = 256;  // two targets per lane: measured faster than one on uneven mixes
-    // work lists: one per precision for the pair sum, one (all systems,
-    // float64) for the potential pass of the diagnostics
-    WorkItem *items[3] = {nullptr, nullptr, nullptr};
-    int32_t nitems[3] = {0, 0, 0};
+    // Device tables are grow-only: a reset for another set of systems reuses
+    // them; an outgrown buffer is kept until the batch is destroyed, since
+    // kernels (or graphs) enqueued earlier may still read it.  Tables are
+    // uploaded from pinned host staging memory with stream-ordered copies.
+    struct Buf { void *p = nullptr; size_t cap = 0; };
+    Buf b_off, b_sc, b_lay, b_tbase, b_seg, b_items[4], b_all, b_part, b_order;
+    int64_t nseg = 0;   // segments of the diagnostics' first pass (b_seg: B + 1 offsets)
+    std::vector<void *> retired;
+    std::vector<hipGraphExec_t> old_graphs;   // replaced graphs, destroyed with the batch
+    char *stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t staged = nullptr;               // end of the last upload from `stage`
+    // Batch plan: R targets per lane, 256 lanes, `split` = source tiles of 256
+    // per chunk (0: whole systems), jsrc = 0 or 3 (or 2) for the NB_MIXED
+    // systems (2 and 3: spatial order).  Float32 systems never split.
+    nbody_plan plan{1, 256, 32, 3};
+    std::vector<BatchSys> lay;
+    BatchSys *lay_dev = nullptr;
+    int64_t *tbase_dev = nullptr;   // B + 1 tile offsets (spatial order)
+    int64_t ntiles = 0;
+    double *part = nullptr;         // split partial sums of all systems
+    void *order = nullptr;          // the batch's spatial order
+    int any_local = 0, any_split = 0;
+    // work lists: [0..2] per precision (LDS source tiles), [3] NB_MIXED
+    // systems in spatial order; one more (all systems, float64, whole
+    // systems) for the potential pass of the diagnostics
+    WorkItem *items[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t nitems[4] = {0, 0, 0, 0};
+    int32_t grid[4] = {0, 0, 0, 0};   // persistent workgroups per list
     WorkItem *items_all = nullptr;
     int32_t nitems_all = 0;
-    int32_t grid[3] = {0, 0, 0};   // persistent workgroups per precision
     int32_t grid_all = 0;
-    int any_fp32 = 0;
     // graph cache: key = state pointers + scheme
     struct Graph { State st; int scheme; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
@@ -262,11 +286,8 @@ struct Timed {
     }
 };
 
-// Pair sum of targets [i0, i1) of one system; kick != 0 fuses the closing
-// half kick v += hdt a.
-nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64_t i0, int64_t i1,
-                      int mode, const nbody_plan &pl, int kick, double hdt, hipStream_t s) {
-    if (i1 <= i0) return NB_OK;
+PairLaunch make_pair_launch(const State &st, const SysConst &sc, int64_t i0, int64_t i1, int mode,
+                            const nbody_plan &pl, int kick, double hdt) {
     PairLaunch P{};
     P.st = st;
     P.sc = sc;
@@ -279,11 +300,40 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
     P.mode = mode;
     P.kick = kick;
     P.hdt = hdt;
+    return P;
+}
+
+// Launches of one pair sum whose scratch is already in place: the spatial
+// order (jsrc 2 and 3, into order_buf), the pair kernel, and the fixed-order
+// reduction of the split partial sums (P.part).
+nbody_status launch_pair_seq(nbody_ctx *ctx, PairLaunch &P, void *order_buf, hipStream_t s) {
+    if (P.jsrc >= 2) {
+        const hipError_t eo = launch_local_order(P.st, P.sc.n, order_buf, &P.lo, s);
+        if (eo != hipSuccess) return hipfail(ctx, eo, "spatial order");
+    }
+    hipError_t e = launch_pair(P, s);
+    if (e != hipSuccess) return hipfail(ctx, e, "pair-sum launch");
+    if (P.split > 1) {
+        e = launch_pair_reduce(P, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "pair-sum reduce launch");
+    }
+    return NB_OK;
+}
+
+// Pair sum of targets [i0, i1) of one system; kick != 0 fuses the closing
+// half kick v += hdt a.
+nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64_t i0, int64_t i1,
+                      int mode, const nbody_plan &pl, int kick, double hdt, hipStream_t s,
+                      bool sorted_rows = false) {
+    if (i1 <= i0) return NB_OK;
+    PairLaunch P = make_pair_launch(st, sc, i0, i1, mode, pl, kick, hdt);
     if (!pair_config_supported(sc.prec, P.R, P.block, P.jsrc, mode))
         return fail(ctx, NB_ENOTSUP, "unsupported plan R=%d block=%d jsrc=%d for mode %d", P.R, P.block, P.jsrc, mode);
     if (P.jsrc >= 2) {
-        if (i0 != 0 || i1 != sc.n)
-            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2 or 3) sums whole systems only");
+        // the rows of a spatially ordered plan are positions in its order
+        if (!sorted_rows && (i0 != 0 || i1 != sc.n))
+            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2 or 3) sums particle-index ranges of "
+                                         "whole systems only (nbody_accel_order_rows takes ranges of its order)");
         nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(sc.n) + 7) / 8, s);
         if (r != NB_OK) return r;
     }
@@ -294,17 +344,7 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
         P.part = ctx->part;
     }
     Timed t(ctx, s, 0, (i1 - i0) * sc.n);
-    if (P.jsrc >= 2) {
-        const hipError_t eo = launch_local_order(st, sc.n, ctx->order, &P.lo, s);
-        if (eo != hipSuccess) return hipfail(ctx, eo, "spatial order");
-    }
-    hipError_t e = launch_pair(P, s);
-    if (e != hipSuccess) return hipfail(ctx, e, "pair-sum launch");
-    if (P.split > 1) {
-        e = launch_pair_reduce(P, s);
-        if (e != hipSuccess) return hipfail(ctx, e, "pair-sum reduce launch");
-    }
-    return NB_OK;
+    return launch_pair_seq(ctx, P, ctx->order, s);
 }
 
 nbody_status kdk_single(nbody_ctx *ctx, const State &st, const SysConst &sc, const nbody_plan &pl,
@@ -342,8 +382,10 @@ nbody_plan mode_plan(nbody_ctx *ctx, int prec, int64_t n, int mode) {
     return pl;
 }
 
+// Cached graphs of a batch whose tables changed: kept until the batch is
+// destroyed (a replay may still be running), never replayed again.
 void destroy_graphs(nbody_batch *b) {
-    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &g : b->graphs) b->old_graphs.push_back(g.exec);
     b->graphs.clear();
 }
 
@@ -352,27 +394,47 @@ bool same_state(const State &a, const State &b) {
            a.vz == b.vz && a.ax == b.ax && a.ay == b.ay && a.az == b.az && a.phi == b.phi;
 }
 
+// Pair sums of every system of a batch (closing half kick of w * dt_sys
+// when kick_scale = w != 0): the batch's spatial order if any system is
+// summed in it, one persistent launch per work list, then the fixed-order
+// reduction of the split partial sums.
+nbody_status batch_pair(nbody_ctx *ctx, nbody_batch *b, const State &st, double kick_scale, hipStream_t s) {
+    BatchLaunch L{};
+    L.st = st;
+    L.st.phi = nullptr;
+    L.sys = b->sc_dev;
+    L.mode = MODE_ACC;
+    L.R = b->plan.R;
+    L.block = 256;
+    L.kick_scale = kick_scale;
+    L.lay = b->lay_dev;
+    L.part = b->part;
+    if (b->any_local) {
+        const hipError_t e =
+            launch_batch_order(st, b->off_dev, b->tbase_dev, b->B, b->ntot, b->ntiles, b->order, &L.lo, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "batched spatial order");
+    }
+    for (int p = 0; p < 4; ++p) {
+        if (b->nitems[p] == 0) continue;
+        L.items = b->items[p];
+        L.nitems = b->nitems[p];
+        L.grid = b->grid[p];
+        L.prec = p == 3 ? P_MIXED : p;
+        const hipError_t e = p == 3 ? launch_pair_local_batched(L, b->plan.jsrc, s) : launch_pair_batched(L, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "batched pair-sum launch");
+    }
+    if (b->any_split) {
+        const hipError_t e = launch_pair_reduce_batched(L, b->off_dev, b->B, b->ntot, s);
+        if (e != hipSuccess) return hipfail(ctx, e, "batched reduce launch");
+    }
+    return NB_OK;
+}
+
 // Enqueue one leapfrog substep of width w * dt_sys for every system.
 nbody_status batch_substep(nbody_ctx *ctx, nbody_batch *b, const State &st, double w, hipStream_t s) {
     hipError_t e = launch_kick_drift_batched(st, b->off_dev, b->sc_dev, b->B, b->ntot, w, s);
     if (e != hipSuccess) return hipfail(ctx, e, "batched kick-drift launch");
-    for (int p = 0; p < 3; ++p) {
-        if (b->nitems[p] == 0) continue;
-        BatchLaunch L{};
-        L.st = st;
-        L.sys = b->sc_dev;
-        L.items = b->items[p];
-        L.nitems = b->nitems[p];
-        L.prec = p;
-        L.mode = MODE_ACC;
-        L.R = b->R;
-        L.block = b->block;
-        L.grid = b->grid[p];
-        L.kick_scale = w;
-        e = launch_pair_batched(L, s);
-        if (e != hipSuccess) return hipfail(ctx, e, "batched pair-sum launch");
-    }
-    return NB_OK;
+    return batch_pair(ctx, b, st, w, s);
 }
 
 nbody_status batch_step_seq(nbody_ctx *ctx, nbody_batch *b, const State &st, int scheme, hipStream_t s) {
@@ -530,6 +592,7 @@ nbody_status nbody_ctx_destroy(nbody_ctx *ctx) {
     if (ctx->integ) (void)hipFree(ctx->integ);
     if (ctx->order) (void)hipFree(ctx->order);
     if (ctx->jvel) (void)hipFree(ctx->jvel);
+    if (ctx->dseg) (void)hipFree(ctx->dseg);
     for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->sysc) (void)hipFree(ctx->sysc);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -571,6 +634,30 @@ nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_
                         (hipStream_t)stream);
     } catch (...) {
         return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_rows");
+    }
+}
+
+nbody_status nbody_accel_order_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm, int64_t k0,
+                                    int64_t k1, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, false);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK) return r;
+        if (k0 < 0 || k1 < k0 || k1 > sys->n)
+            return fail(ctx, NB_EINVAL, "range [%lld, %lld) outside [0, %lld)", (long long)k0, (long long)k1,
+                        (long long)sys->n);
+        if (sys->phi) return fail(ctx, NB_ENOTSUP, "nbody_accel_order_rows does not write phi (sys->phi must be NULL)");
+        if (sys->n == 0 || k0 == k1) return NB_OK;
+        DevGuard g(ctx->device);
+        const nbody_plan pl = mode_plan(ctx, prm->prec, sys->n, MODE_ACC);
+        if (pl.jsrc < 2)
+            return fail(ctx, NB_ENOTSUP, "the plan for n = %lld is not spatially ordered (jsrc %d)", (long long)sys->n,
+                        pl.jsrc);
+        return run_pair(ctx, make_state(sys), make_sysconst(prm, 0, sys->n, 0.0), k0, k1, MODE_ACC, pl, 0, 0.0,
+                        (hipStream_t)stream, true);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_order_rows");
     }
 }
 
@@ -782,7 +869,10 @@ nbody_status nbody_diag(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params
         }
         hipError_t e = launch_set_sysconst(ctx->sysc, sc, s);
         if (e != hipSuccess) return hipfail(ctx, e, "sysconst upload");
-        e = launch_diag_reduce(st, ctx->phi, ctx->sysc, 1, (double *)out_dev, s);
+        const int64_t nseg = diag_segments(n);
+        r = ensure(ctx, &ctx->dseg, &ctx->dseg_cap, 13 * (size_t)std::max<int64_t>(nseg, 1), s);
+        if (r != NB_OK) return r;
+        e = launch_diag_reduce(st, ctx->phi, ctx->sysc, 1, nullptr, nseg, ctx->dseg, (double *)out_dev, s);
         if (e != hipSuccess) return hipfail(ctx, e, "diag reduce launch");
         return NB_OK;
     } catch (...) {
@@ -844,6 +934,145 @@ nbody_status nbody_spatial_order(nbody_ctx *ctx, const nbody_sys *sys, int32_t *
 
 // ---- batched ---------------------------------------------------------------
 
+static bool batch_plan_supported(const nbody_plan &pl) {
+    return pl.block == 256 && (pl.R == 1 || pl.R == 2) && pl.split >= 0 && pl.split <= (1 << 20) &&
+           (pl.jsrc == 0 || pl.jsrc == 2 || pl.jsrc == 3);
+}
+
+static hipError_t grow(nbody_batch *bt, nbody_batch::Buf &b, size_t bytes) {
+    if (b.p && bytes <= b.cap) return hipSuccess;
+    const size_t want = std::max<size_t>(std::max(bytes, b.cap + b.cap / 2), 256);
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return e;
+    if (b.p) bt->retired.push_back(b.p);
+    b.p = p;
+    b.cap = want;
+    return hipSuccess;
+}
+
+// Lay out the batch's current systems (bt->off, bt->sc) under plan pl:
+// per-system chunking, tile offsets, work lists and scratch, uploaded with
+// copies ordered on `stream` (blocking: the call waits for them).  Cached
+// graphs are retired, since their launches hold the old table sizes.
+static nbody_status plan_batch(nbody_ctx *ctx, nbody_batch *bt, const nbody_plan &pl, hipStream_t stream,
+                               bool blocking) {
+    if (!batch_plan_supported(pl))
+        return fail(ctx, NB_EINVAL, "unsupported batch plan R=%d block=%d split=%d jsrc=%d", pl.R, pl.block, pl.split,
+                    pl.jsrc);
+    destroy_graphs(bt);
+    bt->plan = pl;
+    bt->any_local = bt->any_split = 0;
+    const int32_t B = bt->B;
+    const int64_t per = 256LL * pl.R;
+    bt->lay.assign(B, BatchSys{});
+    std::vector<int64_t> tbase(B + 1, 0);
+    int64_t pbase = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const SysConst &c = bt->sc[b];
+        BatchSys &ly = bt->lay[b];
+        ly.local = (c.prec == P_MIXED && pl.jsrc >= 2 && c.n > 0) ? 1 : 0;
+        int64_t split = 1;
+        if (c.prec != P_FP32 && pl.split > 0 && c.n > 0)
+            split = std::max<int64_t>(1, (c.n + 256LL * pl.split - 1) / (256LL * pl.split));
+        ly.split = (int32_t)split;
+        // the chunks of a single launch with this split
+        const int64_t per_chunk = (std::max<int64_t>(c.n, 1) + split - 1) / split;
+        ly.chunk = ((per_chunk + 255) / 256) * 256;
+        ly.tbase = tbase[b];
+        tbase[b + 1] = tbase[b] + (c.n + 255) / 256;
+        ly.pbase = pbase;
+        if (split > 1) pbase += split * 4 * c.n;
+        if (ly.local) bt->any_local = 1;
+        if (split > 1) bt->any_split = 1;
+    }
+    bt->ntiles = tbase[B];
+    std::vector<int64_t> segbase(B + 1, 0);
+    for (int32_t b = 0; b < B; ++b) segbase[b + 1] = segbase[b] + diag_segments(bt->sc[b].n);
+    bt->nseg = segbase[B];
+    // work lists: systems largest first; within a system chunk by chunk, so
+    // workgroups running together share one chunk of sources
+    std::vector<int32_t> order(B);
+    for (int32_t b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return bt->sc[a].n > bt->sc[c].n; });
+    std::vector<WorkItem> lists[4], all;
+    for (int32_t b : order) {
+        const SysConst &c = bt->sc[b];
+        const BatchSys &ly = bt->lay[b];
+        const int li = ly.local ? 3 : c.prec;
+        for (int32_t k = 0; k < ly.split; ++k)
+            for (int64_t i = 0; i < c.n; i += per) lists[li].push_back({b, k, i});
+        for (int64_t i = 0; i < c.n; i += 256) all.push_back({b, 0, i});
+    }
+    // host tables -> one pinned staging area -> device, in stream order
+    struct Up { nbody_batch::Buf *dst; const void *src; size_t bytes; };
+    std::vector<Up> ups{{&bt->b_off, bt->off.data(), sizeof(int64_t) * (B + 1)},
+                        {&bt->b_sc, bt->sc.data(), sizeof(SysConst) * B},
+                        {&bt->b_lay, bt->lay.data(), sizeof(BatchSys) * B},
+                        {&bt->b_tbase, tbase.data(), sizeof(int64_t) * (B + 1)},
+                        {&bt->b_seg, segbase.data(), sizeof(int64_t) * (B + 1)},
+                        {&bt->b_all, all.data(), sizeof(WorkItem) * all.size()}};
+    for (int p = 0; p < 4; ++p) ups.push_back({&bt->b_items[p], lists[p].data(), sizeof(WorkItem) * lists[p].size()});
+    size_t total = 0;
+    for (const Up &u : ups) total += (u.bytes + 255) & ~(size_t)255;
+    if (bt->staged) HIPCHECK(ctx, hipEventSynchronize(bt->staged));  // the staging area is free again
+    else HIPCHECK(ctx, hipEventCreateWithFlags(&bt->staged, hipEventDisableTiming));
+    if (total > bt->stage_cap) {
+        if (bt->stage) (void)hipHostFree(bt->stage);
+        bt->stage = nullptr;
+        bt->stage_cap = 0;
+        const size_t want = std::max(total, bt->stage_cap + bt->stage_cap / 2);
+        HIPCHECK(ctx, hipHostMalloc((void **)&bt->stage, want, hipHostMallocDefault));
+        bt->stage_cap = want;
+    }
+    size_t at = 0;
+    for (const Up &u : ups) {
+        HIPCHECK(ctx, grow(bt, *u.dst, u.bytes));
+        if (u.bytes) {
+            std::memcpy(bt->stage + at, u.src, u.bytes);
+            HIPCHECK(ctx, hipMemcpyAsync(u.dst->p, bt->stage + at, u.bytes, hipMemcpyHostToDevice, stream));
+        }
+        at += (u.bytes + 255) & ~(size_t)255;
+    }
+    HIPCHECK(ctx, hipEventRecord(bt->staged, stream));
+    HIPCHECK(ctx, grow(bt, bt->b_part, sizeof(double) * (size_t)pbase));
+    if (bt->any_local) HIPCHECK(ctx, grow(bt, bt->b_order, batch_order_bytes(bt->ntot, bt->ntiles, B)));
+    bt->off_dev = (int64_t *)bt->b_off.p;
+    bt->sc_dev = (SysConst *)bt->b_sc.p;
+    bt->lay_dev = (BatchSys *)bt->b_lay.p;
+    bt->tbase_dev = (int64_t *)bt->b_tbase.p;
+    bt->part = (double *)bt->b_part.p;
+    bt->order = bt->any_local ? bt->b_order.p : nullptr;
+    for (int p = 0; p < 4; ++p) {
+        bt->items[p] = (WorkItem *)bt->b_items[p].p;
+        bt->nitems[p] = (int32_t)lists[p].size();
+        const int occ = p == 3 ? pair_local_batched_occupancy(pl.R, pl.jsrc) : pair_batched_occupancy(p, pl.R, 256, MODE_ACC);
+        bt->grid[p] = std::min<int32_t>(bt->nitems[p], occ * ctx->cus);
+    }
+    bt->items_all = (WorkItem *)bt->b_all.p;
+    bt->nitems_all = (int32_t)all.size();
+    bt->grid_all = std::min<int32_t>(bt->nitems_all, pair_batched_occupancy(P_FP64, 1, 256, MODE_PHI) * ctx->cus);
+    if (blocking) HIPCHECK(ctx, hipStreamSynchronize(stream));
+    return NB_OK;
+}
+
+// Plan change outside a stream: wait for the device, then lay out and upload.
+static nbody_status build_batch_plan(nbody_ctx *ctx, nbody_batch *bt, const nbody_plan &pl) {
+    HIPCHECK(ctx, hipDeviceSynchronize());  // the old tables may still be in use
+    return plan_batch(ctx, bt, pl, nullptr, true);
+}
+
+// The batch plan pinned for the batch's largest system, else the default:
+// one target per lane, chunks of 32 source tiles, spatial order with the
+// expanded far-tile form for the NB_MIXED systems.
+static nbody_plan default_batch_plan(nbody_ctx *ctx, const nbody_batch *bt) {
+    int64_t nmax = 0;
+    for (const SysConst &c : bt->sc) nmax = std::max(nmax, c.n);
+    auto it = ctx->plans.find({P_MIXED | NB_PLAN_BATCH, ilog2_ceil(nmax)});
+    if (it != ctx->plans.end()) return it->second;
+    return nbody_plan{1, 256, 32, 3};
+}
+
 nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off, const nbody_params *prm,
                                 const double *dt, uint32_t flags, nbody_batch **out) {
     if (!ctx) return NB_EINVAL;
@@ -859,6 +1088,7 @@ nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off, c
         if (r != NB_OK) return fail(ctx, r, "system %d: %s", b, ctx->err.c_str());
         if (dt && !is_finite(dt[b])) return fail(ctx, NB_EINVAL, "dt of system %d is not finite", b);
     }
+    if (off[B] > INT32_MAX) return fail(ctx, NB_EINVAL, "a batch holds < 2^31 particles in all (got %lld)", (long long)off[B]);
     try {
         DevGuard g(ctx->device);
         nbody_batch *bt = new nbody_batch();
@@ -866,52 +1096,13 @@ nbody_status nbody_batch_create(nbody_ctx *ctx, int32_t B, const int64_t *off, c
         bt->flags = flags;
         bt->off.assign(off, off + B + 1);
         bt->ntot = off[B];
-        for (int32_t b = 0; b < B; ++b) {
+        for (int32_t b = 0; b < B; ++b)
             bt->sc.push_back(make_sysconst(&prm[b], off[b], off[b + 1] - off[b], dt ? dt[b] : 0.0));
-            if (prm[b].prec == NB_FP32) bt->any_fp32 = 1;
-        }
-        auto cleanup = [&](nbody_status st, const char *what, hipError_t e) {
+        const nbody_status r = plan_batch(ctx, bt, default_batch_plan(ctx, bt), nullptr, true);
+        if (r != NB_OK) {
+            const std::string msg = ctx->err;
             nbody_batch_destroy(ctx, bt);
-            return e != hipSuccess ? hipfail(ctx, e, what) : fail(ctx, st, "%s", what);
-        };
-        hipError_t e = hipMalloc((void **)&bt->off_dev, sizeof(int64_t) * (B + 1));
-        if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc offsets", e);
-        e = hipMalloc((void **)&bt->sc_dev, sizeof(SysConst) * B);
-        if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc system table", e);
-        e = hipMemcpy(bt->off_dev, bt->off.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return cleanup(NB_EHIP, "copy offsets", e);
-        e = hipMemcpy(bt->sc_dev, bt->sc.data(), sizeof(SysConst) * B, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return cleanup(NB_EHIP, "copy system table", e);
-        // work lists: tiles of block*R targets, largest systems first
-        const int64_t per = (int64_t)bt->block * bt->R;
-        std::vector<int32_t> order(B);
-        for (int32_t b = 0; b < B; ++b) order[b] = b;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return bt->sc[a].n > bt->sc[c].n; });
-        std::vector<WorkItem> lists[3], all;
-        for (int32_t b : order) {
-            const SysConst &c = bt->sc[b];
-            for (int64_t i = c.off; i < c.off + c.n; i += per) {
-                lists[c.prec].push_back({b, 0, i});
-            }
-            for (int64_t i = c.off; i < c.off + c.n; i += 256) all.push_back({b, 0, i});
-        }
-        for (int p = 0; p < 3; ++p) {
-            bt->nitems[p] = (int32_t)lists[p].size();
-            if (lists[p].empty()) continue;
-            e = hipMalloc((void **)&bt->items[p], sizeof(WorkItem) * lists[p].size());
-            if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc work list", e);
-            e = hipMemcpy(bt->items[p], lists[p].data(), sizeof(WorkItem) * lists[p].size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return cleanup(NB_EHIP, "copy work list", e);
-        }
-        for (int p = 0; p < 3; ++p)
-            bt->grid[p] = std::min<int32_t>(bt->nitems[p], pair_batched_occupancy(p, bt->R, bt->block, MODE_ACC) * ctx->cus);
-        bt->nitems_all = (int32_t)all.size();
-        bt->grid_all = std::min<int32_t>(bt->nitems_all, pair_batched_occupancy(P_FP64, 1, 256, MODE_PHI) * ctx->cus);
-        if (!all.empty()) {
-            e = hipMalloc((void **)&bt->items_all, sizeof(WorkItem) * all.size());
-            if (e != hipSuccess) return cleanup(NB_ENOMEM, "hipMalloc work list", e);
-            e = hipMemcpy(bt->items_all, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return cleanup(NB_EHIP, "copy work list", e);
+            return fail(ctx, r, "%s", msg.c_str());
         }
         *out = bt;
         return NB_OK;
@@ -925,19 +1116,70 @@ nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *b) {
     DevGuard g(ctx ? ctx->device : 0);
     (void)hipDeviceSynchronize();
     destroy_graphs(b);
-    for (int p = 0; p < 3; ++p)
-        if (b->items[p]) (void)hipFree(b->items[p]);
-    if (b->items_all) (void)hipFree(b->items_all);
-    if (b->off_dev) (void)hipFree(b->off_dev);
-    if (b->sc_dev) (void)hipFree(b->sc_dev);
+    for (hipGraphExec_t x : b->old_graphs) (void)hipGraphExecDestroy(x);
+    for (nbody_batch::Buf *q : {&b->b_off, &b->b_sc, &b->b_lay, &b->b_tbase, &b->b_seg, &b->b_items[0], &b->b_items[1],
+                                &b->b_items[2], &b->b_items[3], &b->b_all, &b->b_part, &b->b_order})
+        if (q->p) (void)hipFree(q->p);
+    for (void *q : b->retired) (void)hipFree(q);
+    if (b->stage) (void)hipHostFree(b->stage);
+    if (b->staged) (void)hipEventDestroy(b->staged);
     delete b;
     return NB_OK;
+}
+
+nbody_status nbody_batch_reset(nbody_ctx *ctx, nbody_batch *bt, int32_t B, const int64_t *off, const nbody_params *prm,
+                               const double *dt, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    if (!bt) return fail(ctx, NB_EINVAL, "batch is NULL");
+    if (B < 1) return fail(ctx, NB_EINVAL, "B must be >= 1");
+    if (!off || !prm) return fail(ctx, NB_EINVAL, "off and prm must not be NULL");
+    if (off[0] != 0) return fail(ctx, NB_EINVAL, "off[0] must be 0");
+    for (int32_t b = 0; b < B; ++b) {
+        if (off[b + 1] < off[b]) return fail(ctx, NB_EINVAL, "offsets must be non-decreasing (system %d)", b);
+        nbody_status r = check_params(ctx, &prm[b]);
+        if (r != NB_OK) return fail(ctx, r, "system %d: %s", b, ctx->err.c_str());
+        if (dt && !is_finite(dt[b])) return fail(ctx, NB_EINVAL, "dt of system %d is not finite", b);
+    }
+    if (off[B] > INT32_MAX) return fail(ctx, NB_EINVAL, "a batch holds < 2^31 particles in all (got %lld)", (long long)off[B]);
+    if (capturing((hipStream_t)stream)) return fail(ctx, NB_EINVAL, "nbody_batch_reset cannot run under stream capture");
+    try {
+        DevGuard g(ctx->device);
+        bt->B = B;
+        bt->off.assign(off, off + B + 1);
+        bt->ntot = off[B];
+        bt->sc.clear();
+        for (int32_t b = 0; b < B; ++b)
+            bt->sc.push_back(make_sysconst(&prm[b], off[b], off[b + 1] - off[b], dt ? dt[b] : 0.0));
+        return plan_batch(ctx, bt, bt->plan, (hipStream_t)stream, false);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_batch_reset");
+    }
 }
 
 nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *b, nbody_plan *out) {
     if (!ctx) return NB_EINVAL;
     if (!b || !out) return fail(ctx, NB_EINVAL, "batch and out must not be NULL");
-    *out = nbody_plan{b->R, b->block, 1, 0};
+    *out = b->plan;
+    return NB_OK;
+}
+
+nbody_status nbody_batch_set_plan(nbody_ctx *ctx, nbody_batch *b, const nbody_plan *p) {
+    if (!ctx) return NB_EINVAL;
+    if (!b || !p) return fail(ctx, NB_EINVAL, "batch and plan must not be NULL");
+    try {
+        DevGuard g(ctx->device);
+        return build_batch_plan(ctx, b, *p);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_batch_set_plan");
+    }
+}
+
+nbody_status nbody_batch_system_plan(nbody_ctx *ctx, const nbody_batch *b, int32_t sys, nbody_plan *out) {
+    if (!ctx) return NB_EINVAL;
+    if (!b || !out) return fail(ctx, NB_EINVAL, "batch and out must not be NULL");
+    if (sys < 0 || sys >= b->B) return fail(ctx, NB_EINVAL, "system %d outside [0, %d)", sys, b->B);
+    const BatchSys &ly = b->lay[sys];
+    *out = nbody_plan{b->plan.R, 256, ly.split, ly.local ? b->plan.jsrc : 0};
     return NB_OK;
 }
 
@@ -956,26 +1198,8 @@ nbody_status nbody_accel_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys
         if (r != NB_OK || b->ntot == 0) return r;
         DevGuard g(ctx->device);
         hipStream_t s = (hipStream_t)stream;
-        const State st = make_state(all);
-        for (int p = 0; p < 3; ++p) {
-            if (b->nitems[p] == 0) continue;
-            BatchLaunch L{};
-            L.st = st;
-            L.st.phi = nullptr;
-            L.sys = b->sc_dev;
-            L.items = b->items[p];
-            L.nitems = b->nitems[p];
-            L.prec = p;
-            L.mode = MODE_ACC;
-            L.R = b->R;
-            L.block = b->block;
-            L.grid = b->grid[p];
-            L.kick_scale = 0.0;
-            Timed t(ctx, s, 0, 0);
-            hipError_t e = launch_pair_batched(L, s);
-            if (e != hipSuccess) return hipfail(ctx, e, "batched pair-sum launch");
-        }
-        return NB_OK;
+        Timed t(ctx, s, 0, 0);
+        return batch_pair(ctx, b, make_state(all), 0.0, s);
     } catch (...) {
         return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_batched");
     }
@@ -1035,7 +1259,10 @@ nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys 
             hipError_t e = launch_pair_batched(L, s);
             if (e != hipSuccess) return hipfail(ctx, e, "batched potential launch");
         }
-        hipError_t e = launch_diag_reduce(st, ctx->phi, b->sc_dev, b->B, (double *)out_dev, s);
+        r = ensure(ctx, &ctx->dseg, &ctx->dseg_cap, 13 * (size_t)std::max<int64_t>(b->nseg, 1), s);
+        if (r != NB_OK) return r;
+        hipError_t e = launch_diag_reduce(st, ctx->phi, b->sc_dev, b->B, (const int64_t *)b->b_seg.p, b->nseg,
+                                          ctx->dseg, (double *)out_dev, s);
         if (e != hipSuccess) return hipfail(ctx, e, "batched diag launch");
         return NB_OK;
     } catch (...) {
@@ -1050,18 +1277,23 @@ static nbody_status split_class(nbody_ctx *ctx, int32_t code, int *prec, int *cl
     *prec = code & 0xff;
     *cls = code & ~0xff;
     if (*prec < 0 || *prec > 2) return fail(ctx, NB_EINVAL, "unknown precision %d", *prec);
-    if (*cls != NB_PLAN_ACCEL && *cls != NB_PLAN_POTENTIAL && *cls != NB_PLAN_JERK)
+    if (*cls != NB_PLAN_ACCEL && *cls != NB_PLAN_POTENTIAL && *cls != NB_PLAN_JERK && *cls != NB_PLAN_BATCH)
         return fail(ctx, NB_EINVAL, "unknown plan class 0x%x", *cls);
     return NB_OK;
 }
 
 static nbody_plan effective_plan(nbody_ctx *ctx, int prec, int cls, int64_t n) {
+    if (cls == NB_PLAN_BATCH) {
+        auto it = ctx->plans.find({prec | cls, ilog2_ceil(n)});
+        return it != ctx->plans.end() ? it->second : nbody_plan{1, 256, 32, 3};
+    }
     if (cls == NB_PLAN_POTENTIAL) return mode_plan(ctx, prec, n, MODE_PHI);
     if (cls == NB_PLAN_JERK) return jerk_plan(ctx, prec, n);
     return plan_for(ctx, prec, n);
 }
 
 static bool class_plan_supported(int prec, int cls, const nbody_plan &p) {
+    if (cls == NB_PLAN_BATCH) return batch_plan_supported(p);
     if (p.split < 1 || p.split > 1024) return false;
     if (cls == NB_PLAN_JERK)
         return p.block == 256 && (p.R == 1 || p.R == 2) && (p.jsrc == 0 || (p.jsrc == 2 && prec == P_MIXED));
@@ -1095,111 +1327,238 @@ nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec_class, int64_t n, const
     return NB_OK;
 }
 
+}  // extern "C"
+
+// ---- autotuning ------------------------------------------------------------
+
+// Candidate plans of a kernel class for n particles: the key's current plan
+// first, then for NB_MIXED the spatially ordered plans, then the others
+// (every R, block = j-tile length and source split the kernels take).
+static std::vector<nbody_plan> tune_candidates(nbody_ctx *ctx, int prec, int cls, int64_t n) {
+    std::vector<nbody_plan> cand;
+    auto add = [&](const nbody_plan &c) {
+        if (!class_plan_supported(prec, cls, c)) return;
+        for (const nbody_plan &d : cand)
+            if (d.R == c.R && d.block == c.block && d.split == c.split && d.jsrc == c.jsrc) return;
+        cand.push_back(c);
+    };
+    add(effective_plan(ctx, prec, cls, n));
+    std::vector<int> jsrcs{0, 1};
+    if (cls == NB_PLAN_JERK) jsrcs = prec == P_MIXED ? std::vector<int>{2, 0} : std::vector<int>{0};
+    else if (prec == P_MIXED && cls == NB_PLAN_ACCEL) jsrcs = {3, 2, 0, 1};
+    // splits up to 64 while each chunk keeps at least two source tiles
+    const int max_split = prec == P_FP32 ? 1 : 64;
+    for (int jsrc : jsrcs)
+        for (int block : {256, 128})
+            for (int R : {1, 2, 4})
+                for (int split = 1; split <= max_split; split *= 2) {
+                    if (split > 1 && n / split < 2LL * block) continue;
+                    add(nbody_plan{R, block, split, jsrc});
+                }
+    return cand;
+}
+
+// Time candidates (one warm-up and two timed launches each, on the NULL
+// stream) until budget_ms is spent (budget_ms <= 0: all); *best = fastest.
+template <class Launch>
+static nbody_status time_candidates(nbody_ctx *ctx, const std::vector<nbody_plan> &cand, double budget_ms,
+                                    Launch launch, nbody_plan *best) {
+    hipEvent_t a = nullptr, bev = nullptr;
+    HIPCHECK(ctx, hipEventCreate(&a));
+    HIPCHECK(ctx, hipEventCreate(&bev));
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    double spent = 0.0, best_ms = -1.0;
+    nbody_status result = NB_OK;
+    for (size_t c = 0; c < cand.size(); ++c) {
+        if (c > 0 && budget_ms > 0 && spent >= budget_ms) break;
+        // warm-up (and scratch sizing), timed to choose how many launches
+        // make a measurement of at least 20 ms (2 to 16)
+        (void)hipEventRecord(a, nullptr);
+        result = launch(cand[c]);
+        (void)hipEventRecord(bev, nullptr);
+        if (result != NB_OK) break;
+        hipError_t e = hipEventSynchronize(bev);
+        if (e != hipSuccess) { result = hipfail(ctx, e, "autotune sync"); break; }
+        float ms1 = 0.0f;
+        (void)hipEventElapsedTime(&ms1, a, bev);
+        const int reps = std::max(2, std::min(16, (int)std::ceil(20.0 / std::max(ms1, 1e-3f))));
+        (void)hipEventRecord(a, nullptr);
+        for (int k = 0; k < reps && result == NB_OK; ++k) result = launch(cand[c]);
+        (void)hipEventRecord(bev, nullptr);
+        if (result != NB_OK) break;
+        e = hipEventSynchronize(bev);
+        if (e != hipSuccess) { result = hipfail(ctx, e, "autotune sync"); break; }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, a, bev);
+        spent += ms + ms1;
+        const double per = ms / reps;
+        if (best_ms < 0 || per < best_ms) { best_ms = per; *best = cand[c]; }
+    }
+    ctx->prof = prof;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(bev);
+    return result;
+}
+
+// Tune the plan of (prec, class) on the whole system st (all n sources),
+// pin the fastest for the key of n and leave st's outputs as that plan
+// gives them.
+static nbody_status autotune_on(nbody_ctx *ctx, int prec, int cls, const nbody_sys *sys, const nbody_params *prm,
+                                double budget_ms, nbody_plan *out) {
+    const int64_t n = sys->n;
+    nbody_params p = *prm;
+    p.prec = prec;
+    const SysConst sc = make_sysconst(&p, 0, n, 0.0);
+    // outputs the call does not own: the jerks or the potential
+    double *tmp = nullptr;
+    if (cls == NB_PLAN_JERK || cls == NB_PLAN_POTENTIAL)
+        HIPCHECK(ctx, hipMalloc((void **)&tmp, sizeof(double) * 3 * (size_t)n));
+    State st = make_state(sys);
+    st.phi = nullptr;
+    State sp = st;
+    sp.phi = tmp;
+    JerkLaunch J{};
+    J.x = sys->x; J.y = sys->y; J.z = sys->z; J.vx = sys->vx; J.vy = sys->vy; J.vz = sys->vz; J.m = sys->m;
+    J.ax = sys->ax; J.ay = sys->ay; J.az = sys->az;
+    J.jx = tmp; J.jy = tmp + n; J.jz = tmp + 2 * n;
+    J.sc = sc;
+    J.i0 = 0;
+    J.i1 = n;
+    auto launch = [&](const nbody_plan &pl) -> nbody_status {
+        if (cls == NB_PLAN_JERK) {
+            JerkLaunch Jc = J;
+            return run_jerk(ctx, Jc, pl, nullptr);
+        }
+        if (cls == NB_PLAN_POTENTIAL) return run_pair(ctx, sp, sc, 0, n, MODE_PHI, pl, 0, 0.0, nullptr);
+        return run_pair(ctx, st, sc, 0, n, MODE_ACC, pl, 0, 0.0, nullptr);
+    };
+    const std::vector<nbody_plan> cand = tune_candidates(ctx, prec, cls, n);
+    nbody_plan best = cand.front();
+    nbody_status r = time_candidates(ctx, cand, budget_ms, launch, &best);
+    if (r == NB_OK) r = launch(best);  // the outputs as the pinned plan gives them
+    (void)hipDeviceSynchronize();
+    if (tmp) (void)hipFree(tmp);
+    if (r != NB_OK) return r;
+    ctx->plans[{prec | cls, ilog2_ceil(n)}] = best;
+    if (out) *out = best;
+    return NB_OK;
+}
+
+extern "C" {
+
+nbody_status nbody_autotune_sys(nbody_ctx *ctx, int32_t prec_class, const nbody_sys *sys, const nbody_params *prm,
+                                double budget_ms, nbody_plan *out) {
+    if (!ctx) return NB_EINVAL;
+    int prec = 0, cls = 0;
+    nbody_status r = split_class(ctx, prec_class, &prec, &cls);
+    if (r != NB_OK) return r;
+    if (cls == NB_PLAN_BATCH) return fail(ctx, NB_EINVAL, "batch plans are tuned by nbody_batch_autotune");
+    r = check_sys(ctx, sys, cls == NB_PLAN_JERK);
+    if (r == NB_OK) r = check_params(ctx, prm);
+    if (r != NB_OK) return r;
+    if (sys->n < 1) return fail(ctx, NB_EINVAL, "n must be >= 1");
+    if (!is_finite(budget_ms)) return fail(ctx, NB_EINVAL, "budget_ms must be finite");
+    try {
+        DevGuard g(ctx->device);
+        return autotune_on(ctx, prec, cls, sys, prm, budget_ms, out);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_autotune_sys");
+    }
+}
+
 nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec_class, int64_t n, double budget_ms, nbody_plan *out) {
     if (!ctx) return NB_EINVAL;
     int prec = 0, cls = 0;
     nbody_status r0 = split_class(ctx, prec_class, &prec, &cls);
     if (r0 != NB_OK) return r0;
+    if (cls == NB_PLAN_BATCH) return fail(ctx, NB_EINVAL, "batch plans are tuned by nbody_batch_autotune");
     if (n < 1 || n > INT32_MAX) return fail(ctx, NB_EINVAL, "n must be in [1, 2^31)");
     if (!is_finite(budget_ms)) return fail(ctx, NB_EINVAL, "budget_ms must be finite");
     try {
         DevGuard g(ctx->device);
-        // synthetic particles: a uniform cube, equal masses, small random
-        // velocities, in one scratch block:
-        // x y z m | ax ay az | vx vy vz | phi | jx jy jz
+        // synthetic thin exponential disk (scale length 1, cut at 4, sech^2
+        // layers of thickness 0.1, near-circular motion), equal masses
         const size_t nn = (size_t)n;
         double *buf = nullptr;
-        HIPCHECK(ctx, hipMalloc((void **)&buf, sizeof(double) * 14 * nn));
-        std::vector<double> h(14 * nn, 0.0);
+        HIPCHECK(ctx, hipMalloc((void **)&buf, sizeof(double) * 10 * nn));
+        std::vector<double> h(10 * nn, 0.0);
         uint64_t s = 0x9E3779B97F4A7C15ULL;
         auto uni = [&]() {
             s = s * 6364136223846793005ULL + 1442695040888963407ULL;
-            return (double)(s >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+            return ((double)(s >> 11) + 0.5) * (1.0 / 9007199254740992.0);
         };
-        for (size_t i = 0; i < 3 * nn; ++i) h[i] = uni();
-        for (size_t i = 0; i < nn; ++i) h[3 * nn + i] = 1.0 / (double)n;
-        for (size_t i = 7 * nn; i < 10 * nn; ++i) h[i] = 0.1 * uni();
-        hipError_t e = hipMemcpy(buf, h.data(), sizeof(double) * 14 * nn, hipMemcpyHostToDevice);
-        if (e != hipSuccess) { (void)hipFree(buf); return hipfail(ctx, e, "autotune upload"); }
-        State st{};
-        st.x = buf; st.y = buf + n; st.z = buf + 2 * n; st.m = buf + 3 * n;
-        st.ax = buf + 4 * n; st.ay = buf + 5 * n; st.az = buf + 6 * n;
-        st.vx = buf + 7 * n; st.vy = buf + 8 * n; st.vz = buf + 9 * n;
-        double *phi = buf + 10 * n;
-        nbody_params p{1.0, 0.01, prec, 0, 0.0, 0.0};
-        SysConst sc = make_sysconst(&p, 0, n, 0.0);
-        // long source sweeps behave alike, so large systems are timed
-        // against a prefix of the sources with the full target grid
-        const int64_t nsrc = std::min<int64_t>(n, 32768);
-        sc.n = nsrc;
-        JerkLaunch J{};
-        J.x = st.x; J.y = st.y; J.z = st.z; J.vx = st.vx; J.vy = st.vy; J.vz = st.vz; J.m = st.m;
-        J.ax = st.ax; J.ay = st.ay; J.az = st.az;
-        J.jx = buf + 11 * n; J.jy = buf + 12 * n; J.jz = buf + 13 * n;
-        J.sc = sc;
-        J.i0 = 0;
-        J.i1 = n;
-        State sp = st;
-        sp.phi = phi;
-        auto launch = [&](const nbody_plan &pl) -> nbody_status {
-            if (cls == NB_PLAN_JERK) return run_jerk(ctx, J, pl, nullptr);
-            if (cls == NB_PLAN_POTENTIAL) return run_pair(ctx, sp, sc, 0, n, MODE_PHI, pl, 0, 0.0, nullptr);
-            return run_pair(ctx, st, sc, 0, n, MODE_ACC, pl, 0, 0.0, nullptr);
-        };
-        std::vector<nbody_plan> cand;
-        const nbody_plan base = effective_plan(ctx, prec, cls, n);
-        // a spatially ordered plan sums whole systems only, and the sweep
-        // above covers a prefix of the sources when n > nsrc
-        if (base.jsrc < 2 || n <= nsrc) cand.push_back(base);
-        const int max_split = prec == P_FP32 ? 1 : 64;
-        for (int jsrc = 0; jsrc <= (cls == NB_PLAN_JERK ? 0 : 1); ++jsrc)
-            for (int block : {256, 128})
-                for (int R : {1, 2, 4})
-                    for (int split = 1; split <= max_split; split *= 2) {
-                        nbody_plan c{R, block, split, jsrc};
-                        if (!class_plan_supported(prec, cls, c)) continue;
-                        const int64_t nblk = (n + (int64_t)block * R - 1) / ((int64_t)block * R);
-                        if (split > 1 && (nblk * split > 16LL * ctx->cus || n / split < 2LL * block)) continue;
-                        if (c.R == base.R && c.block == base.block && c.split == base.split && c.jsrc == base.jsrc) continue;
-                        cand.push_back(c);
-                    }
-        hipEvent_t a, bev;
-        HIPCHECK(ctx, hipEventCreate(&a));
-        HIPCHECK(ctx, hipEventCreate(&bev));
-        const bool prof = ctx->prof;
-        ctx->prof = false;
-        double spent = 0.0, best_rate = -1.0;
-        nbody_plan best = cand.empty() ? base : cand[0];
-        nbody_status result = NB_OK;
-        for (size_t c = 0; c < cand.size(); ++c) {
-            if (c > 0 && budget_ms > 0 && spent >= budget_ms) break;
-            const nbody_plan &pl = cand[c];
-            float ms = 0.0f;
-            result = launch(pl);  // warm-up
-            if (result != NB_OK) break;
-            (void)hipEventRecord(a, nullptr);
-            const int reps = 2;
-            for (int k = 0; k < reps && result == NB_OK; ++k) result = launch(pl);
-            (void)hipEventRecord(bev, nullptr);
-            if (result != NB_OK) break;
-            e = hipEventSynchronize(bev);
-            if (e != hipSuccess) { result = hipfail(ctx, e, "autotune sync"); break; }
-            (void)hipEventElapsedTime(&ms, a, bev);
-            spent += ms * 1.5;
-            const double rate = (double)n * (double)nsrc * reps / (ms * 1e-3);
-            if (rate > best_rate) { best_rate = rate; best = pl; }
+        for (size_t i = 0; i < nn; ++i) {
+            double R;
+            do R = -std::log(uni() * uni()); while (R > 4.0);  // surface density ~ exp(-R)
+            const double ph = 6.283185307179586 * uni();
+            const double z = 0.1 * std::atanh(std::min(0.999999, std::max(-0.999999, 2.0 * uni() - 1.0)));
+            const double v = std::sqrt(R / (1.0 + R));
+            h[i] = R * std::cos(ph); h[nn + i] = R * std::sin(ph); h[2 * nn + i] = z;
+            h[3 * nn + i] = -v * std::sin(ph); h[4 * nn + i] = v * std::cos(ph); h[5 * nn + i] = 0.01 * (uni() - 0.5);
+            h[6 * nn + i] = 1.0 / (double)n;
         }
-        ctx->prof = prof;
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(bev);
+        hipError_t e = hipMemcpy(buf, h.data(), sizeof(double) * 7 * nn, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipFree(buf); return hipfail(ctx, e, "autotune upload"); }
+        nbody_sys sys{};
+        sys.n = n;
+        sys.x = buf; sys.y = buf + n; sys.z = buf + 2 * n;
+        sys.vx = buf + 3 * n; sys.vy = buf + 4 * n; sys.vz = buf + 5 * n;
+        sys.m = buf + 6 * n;
+        sys.ax = buf + 7 * n; sys.ay = buf + 8 * n; sys.az = buf + 9 * n;
+        sys.phi = nullptr;
+        nbody_params p{1.0, 0.02, prec, 0, 0.0, 0.0};
+        const nbody_status r = autotune_on(ctx, prec, cls, &sys, &p, budget_ms, out);
         (void)hipDeviceSynchronize();
         (void)hipFree(buf);
-        if (result != NB_OK) return result;
-        ctx->plans[{prec | cls, ilog2_ceil(n)}] = best;
+        return r;
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_autotune");
+    }
+}
+
+nbody_status nbody_batch_autotune(nbody_ctx *ctx, nbody_batch *b, const nbody_sys *all, double budget_ms,
+                                  nbody_plan *out) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_batch_sys(ctx, b, all, false);
+        if (r != NB_OK) return r;
+        if (!is_finite(budget_ms)) return fail(ctx, NB_EINVAL, "budget_ms must be finite");
+        DevGuard g(ctx->device);
+        bool any_mixed = false;
+        int64_t nmax = 0;
+        for (const SysConst &c : b->sc) {
+            any_mixed |= c.prec == P_MIXED;
+            nmax = std::max(nmax, c.n);
+        }
+        std::vector<nbody_plan> cand{b->plan};
+        for (int jsrc : any_mixed ? std::vector<int>{3, 2, 0} : std::vector<int>{0})
+            for (int R : {1, 2})
+                for (int split : {0, 8, 16, 32, 64}) {
+                    const nbody_plan c{R, 256, split, jsrc};
+                    bool dup = false;
+                    for (const nbody_plan &d : cand)
+                        dup |= d.R == c.R && d.split == c.split && d.jsrc == c.jsrc;
+                    if (!dup) cand.push_back(c);
+                }
+        const State st = make_state(all);
+        auto launch = [&](const nbody_plan &pl) -> nbody_status {
+            if (pl.R != b->plan.R || pl.split != b->plan.split || pl.jsrc != b->plan.jsrc || !b->lay_dev) {
+                const nbody_status rb = build_batch_plan(ctx, b, pl);
+                if (rb != NB_OK) return rb;
+            }
+            return batch_pair(ctx, b, st, 0.0, nullptr);
+        };
+        nbody_plan best = cand.front();
+        r = time_candidates(ctx, cand, budget_ms, launch, &best);
+        if (r == NB_OK) r = launch(best);
+        (void)hipDeviceSynchronize();
+        if (r != NB_OK) return r;
+        ctx->plans[{P_MIXED | NB_PLAN_BATCH, ilog2_ceil(nmax)}] = best;
         if (out) *out = best;
         return NB_OK;
     } catch (...) {
-        return fail(ctx, NB_ENOMEM, "host exception in nbody_autotune");
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_batch_autotune");
     }
 }
 

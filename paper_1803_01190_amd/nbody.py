@@ -23,8 +23,8 @@ NB_OK, NB_EINVAL, NB_ENOMEM, NB_EHIP, NB_ENOTSUP = 0, -1, -2, -3, -4
 NB_FP64, NB_MIXED, NB_FP32 = 0, 1, 2
 NB_BATCH_GRAPH = 1
 PREC = {"fp64": NB_FP64, "mixed": NB_MIXED, "fp32": NB_FP32}
-NB_PLAN_ACCEL, NB_PLAN_POTENTIAL, NB_PLAN_JERK = 0x000, 0x100, 0x200
-PLAN_CLASS = {"accel": NB_PLAN_ACCEL, "potential": NB_PLAN_POTENTIAL, "jerk": NB_PLAN_JERK}
+NB_PLAN_ACCEL, NB_PLAN_POTENTIAL, NB_PLAN_JERK, NB_PLAN_BATCH = 0x000, 0x100, 0x200, 0x300
+PLAN_CLASS = {"accel": NB_PLAN_ACCEL, "potential": NB_PLAN_POTENTIAL, "jerk": NB_PLAN_JERK, "batch": NB_PLAN_BATCH}
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "ax", "ay", "az")
 
 
@@ -73,6 +73,7 @@ def _load():
         "nbody_ctx_destroy": ([P]),
         "nbody_accel": ([P, S, PR, V]),
         "nbody_accel_rows": ([P, S, PR, I64, I64, V]),
+        "nbody_accel_order_rows": ([P, S, PR, I64, I64, V]),
         "nbody_step_kdk": ([P, S, PR, D, I64, V]),
         "nbody_step_o4": ([P, S, PR, D, I64, V]),
         "nbody_diag": ([P, S, PR, V, V]),
@@ -84,7 +85,10 @@ def _load():
         "nbody_batch_create": ([P, I32, ctypes.POINTER(I64), PR, ctypes.POINTER(D), ctypes.c_uint32,
                                 ctypes.POINTER(P)]),
         "nbody_batch_destroy": ([P, P]),
+        "nbody_batch_reset": ([P, P, I32, ctypes.POINTER(I64), PR, ctypes.POINTER(D), V]),
         "nbody_batch_get_plan": ([P, P, ctypes.POINTER(c_plan)]),
+        "nbody_batch_set_plan": ([P, P, ctypes.POINTER(c_plan)]),
+        "nbody_batch_system_plan": ([P, P, I32, ctypes.POINTER(c_plan)]),
         "nbody_accel_batched": ([P, P, S, V]),
         "nbody_step_kdk_batched": ([P, P, S, I64, V]),
         "nbody_step_o4_batched": ([P, P, S, I64, V]),
@@ -92,6 +96,8 @@ def _load():
         "nbody_plan_get": ([P, I32, I64, ctypes.POINTER(c_plan)]),
         "nbody_plan_set": ([P, I32, I64, ctypes.POINTER(c_plan)]),
         "nbody_autotune": ([P, I32, I64, D, ctypes.POINTER(c_plan)]),
+        "nbody_autotune_sys": ([P, I32, S, PR, D, ctypes.POINTER(c_plan)]),
+        "nbody_batch_autotune": ([P, P, S, D, ctypes.POINTER(c_plan)]),
         "nbody_profile_enable": ([P, ctypes.c_int]),
         "nbody_profile_read": ([P, ctypes.POINTER(c_profile)]),
     }
@@ -204,6 +210,12 @@ def nbody_accel(ctx, sys: System, prm: Params, stream=None):
     _check(ctx, _lib.nbody_accel(ctx, ctypes.byref(cs), ctypes.byref(cp), _stream(stream)))
 
 
+def nbody_accel_order_rows(ctx, sys: System, prm: Params, k0: int, k1: int, stream=None):
+    cs, cp = sys.c(), prm.c()
+    _check(ctx, _lib.nbody_accel_order_rows(ctx, ctypes.byref(cs), ctypes.byref(cp), int(k0), int(k1),
+                                            _stream(stream)))
+
+
 def nbody_accel_rows(ctx, sys: System, prm: Params, i0: int, i1: int, stream=None):
     cs, cp = sys.c(), prm.c()
     _check(ctx, _lib.nbody_accel_rows(ctx, ctypes.byref(cs), ctypes.byref(cp), int(i0), int(i1),
@@ -290,6 +302,14 @@ def nbody_batch_create(ctx, off, prms, dts=None, flags: int = 0):
     return h
 
 
+def nbody_batch_reset(ctx, batch, off, prms, dts=None, stream=None):
+    B = len(off) - 1
+    off_a = (ctypes.c_int64 * (B + 1))(*[int(v) for v in off])
+    prm_a = (c_params * B)(*[p.c() for p in prms])
+    dt_a = (ctypes.c_double * B)(*[float(v) for v in dts]) if dts is not None else None
+    _check(ctx, _lib.nbody_batch_reset(ctx, batch, B, off_a, prm_a, dt_a, _stream(stream)))
+
+
 def nbody_batch_destroy(ctx, batch):
     _check(ctx, _lib.nbody_batch_destroy(ctx, batch))
 
@@ -297,6 +317,17 @@ def nbody_batch_destroy(ctx, batch):
 def nbody_batch_get_plan(ctx, batch) -> dict:
     p = c_plan()
     _check(ctx, _lib.nbody_batch_get_plan(ctx, batch, ctypes.byref(p)))
+    return p.as_dict()
+
+
+def nbody_batch_set_plan(ctx, batch, plan: dict):
+    p = c_plan(int(plan["R"]), int(plan["block"]), int(plan["split"]), int(plan.get("jsrc", 0)))
+    _check(ctx, _lib.nbody_batch_set_plan(ctx, batch, ctypes.byref(p)))
+
+
+def nbody_batch_system_plan(ctx, batch, sys: int) -> dict:
+    p = c_plan()
+    _check(ctx, _lib.nbody_batch_system_plan(ctx, batch, int(sys), ctypes.byref(p)))
     return p.as_dict()
 
 
@@ -373,6 +404,21 @@ def load_plans(ctx, path: str = TUNED_PLANS, arch: str = "gfx950") -> int:
 def nbody_autotune(ctx, prec: int, n: int, budget_ms: float = 2000.0) -> dict:
     p = c_plan()
     _check(ctx, _lib.nbody_autotune(ctx, int(prec), int(n), float(budget_ms), ctypes.byref(p)))
+    return p.as_dict()
+
+
+def nbody_autotune_sys(ctx, prec: int, sys: System, prm: Params, budget_ms: float = 2000.0) -> dict:
+    p = c_plan()
+    cs, cp = sys.c(), prm.c()
+    _check(ctx, _lib.nbody_autotune_sys(ctx, int(prec), ctypes.byref(cs), ctypes.byref(cp), float(budget_ms),
+                                        ctypes.byref(p)))
+    return p.as_dict()
+
+
+def nbody_batch_autotune(ctx, batch, all_sys: System, budget_ms: float = 4000.0) -> dict:
+    p = c_plan()
+    cs = all_sys.c()
+    _check(ctx, _lib.nbody_batch_autotune(ctx, batch, ctypes.byref(cs), float(budget_ms), ctypes.byref(p)))
     return p.as_dict()
 
 

@@ -21,6 +21,13 @@ from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional
 
 STATE_BYTES_PER_PARTICLE = 80  # x y z vx vy vz m ax ay az, float64
+# Device bytes a request holds while active, per particle: its state twice
+# (while the pack is rebuilt, the old pack, the new pack and newly admitted
+# requests' own arrays are alive together), the batch's spatial order (keys,
+# permutation, sorted positions and masses, tile boxes: about 64 B) and the
+# diagnostics' potential (8 B); the partial sums of its source chunks are
+# added per request (see GpuBackend.footprint).
+ACTIVE_BYTES_PER_PARTICLE = 2 * STATE_BYTES_PER_PARTICLE + 64 + 8
 
 
 @dataclass
@@ -117,13 +124,15 @@ class Scheduler:
 
     def __init__(self, backend: Backend, hbm_budget: int, max_slots: int = 256,
                  max_tick_steps: int = 25, clock: Optional[Callable[[], float]] = None,
-                 sleep: Optional[Callable[[float], None]] = None):
+                 sleep: Optional[Callable[[float], None]] = None,
+                 progress: Optional[Callable[[dict], None]] = None):
         self.b = backend
         self.budget = int(hbm_budget)
         self.max_slots = max_slots
         self.max_tick = max(1, int(max_tick_steps))
         self.clock = clock or time.monotonic
         self.sleep = sleep or time.sleep
+        self.progress = progress  # called after every tick with counts and the time
 
     def run(self, requests: List[Request]) -> Stats:
         st = Stats()
@@ -193,6 +202,9 @@ class Scheduler:
                     st.results.append(res)
                     used -= a["fp"]
                     del active[rid]
+            if self.progress is not None:
+                self.progress({"t": now(), "active": len(active), "waiting": len(waiting), "pending": len(pending),
+                               "done": len(st.results), "used_bytes": used})
         st.wall = now()
         st.results.sort(key=lambda r: r.id)
         return st
@@ -201,15 +213,15 @@ class Scheduler:
 # ---------------------------------------------------------------------------
 class GpuBackend(Backend):
     """Drives libnbody.so: active requests live packed back to back in one set
-    of device arrays; the pack is rebuilt (device-to-device copies) whenever
-    the set of active requests changes, together with its batch plan.  HIP
-    graph replay is off by default here: the set of active requests changes
-    every few steps, and each change would need a new capture."""
+    of device arrays and one batch.  Whenever the set of active requests
+    changes, the pack is rebuilt with device-to-device copies on the loop's
+    stream and the batch is re-laid out for the new set with
+    ``nbody_batch_reset`` (its device tables are reused and refilled by
+    stream-ordered copies; nothing synchronises the device).  Between changes,
+    steps replay a HIP graph captured for the current set (``graph``)."""
 
-    BATCH_PLAN = {"R": 2, "block": 256, "split": 1, "jsrc": 0}
-
-    def __init__(self, ctx, device="cuda", graph: bool = False, keep_state: bool = True,
-                 diagnostics: bool = True):
+    def __init__(self, ctx, device="cuda", graph: bool = True, keep_state: bool = True,
+                 diagnostics: bool = True, plan: Optional[dict] = None):
         import torch
 
         from . import nbody as nb
@@ -222,19 +234,27 @@ class GpuBackend(Backend):
         self.keep_state = keep_state
         self.diagnostics = diagnostics
         self.halo = wl.default_halo()
+        # the batch plan of the loop: the one pinned for systems up to 2^20,
+        # else the library's default
+        self.plan = dict(plan) if plan is not None else nb.nbody_plan_get(ctx, nb.NB_MIXED | nb.NB_PLAN_BATCH, 1 << 20)
         # all device work of the loop goes to one non-blocking stream (default
-        # priority), so the library's blocking table uploads on the legacy
-        # stream do not wait for running steps
+        # priority)
         self.stream = torch.cuda.Stream()
-        self.retired: list = []           # batch plans freed later (freeing synchronises)
         self.live: Dict[int, dict] = {}   # handle -> {req, sys (own arrays or view), prm}
         self.order: List[int] = []        # handles in pack order
         self.pack = None                  # packed System
         self.batch = None
         self.dirty = True
 
+    def _chunks(self, n: int, fp32: bool = False) -> int:
+        """Source chunks of an n-particle system under the loop's batch plan."""
+        c = int(self.plan["split"])
+        return 1 if (fp32 or c == 0) else max(1, -(-int(n) // (256 * c)))
+
     def footprint(self, req: Request) -> int:
-        return STATE_BYTES_PER_PARTICLE * int(req.n)
+        n = int(req.n)
+        k = self._chunks(n)
+        return ACTIVE_BYTES_PER_PARTICLE * n + (32 * k * n if k > 1 else 0)
 
     def _params(self, req: Request):
         nb, h = self.nb, self.halo
@@ -243,16 +263,23 @@ class GpuBackend(Backend):
         return nb.Params(G=1.0, eps=eps, prec=nb.NB_FP64 if req.fp64 else nb.NB_MIXED, halo=disk,
                          halo_v2=h.v2 if disk else 0.0, halo_rc=h.rc if disk else 0.0)
 
+    def _alone_plan(self, prm, n: int) -> dict:
+        """The single-system plan that gives this system's sums bitwise as the
+        batch does (its chunk count; spatial order for NB_MIXED systems when
+        the batch plan uses it)."""
+        nb = self.nb
+        return {"R": int(self.plan["R"]), "block": 256, "split": self._chunks(n, prm.prec == nb.NB_FP32),
+                "jsrc": int(self.plan["jsrc"]) if prm.prec == nb.NB_MIXED else 0}
+
     def admit(self, req: Request):
         nb = self.nb
         ic = req.ic if req.ic is not None else self.wl.make(req.model, req.n, req.seed)
         with self.torch.cuda.stream(self.stream):
             s = nb.System.from_arrays(ic, device=self.device)
         prm = self._params(req)
-        # a(t0) under the plan every batch uses (R 2, 256 lanes, no split,
-        # LDS), which gives the same bits as the batched kernel; this avoids
-        # creating (and synchronously destroying) a one-system batch
-        nb.nbody_plan_set(self.ctx, prm.prec, req.n, self.BATCH_PLAN)
+        # a(t0) under the plan the batch takes for this system, which gives the
+        # bits the batched kernels give
+        nb.nbody_plan_set(self.ctx, prm.prec, req.n, self._alone_plan(prm, req.n))
         try:
             nb.nbody_accel(self.ctx, s, prm, stream=self.stream)
         finally:
@@ -281,23 +308,16 @@ class GpuBackend(Backend):
             view.t = {f: pack.t[f][off[k]:off[k + 1]] for f in nb.FIELDS}
             view.t["phi"] = None
             self.live[h]["sys"] = view
-        if self.batch is not None:
-            self._retire(self.batch)
-        self.batch = nb.nbody_batch_create(self.ctx, off, [self.live[h]["prm"] for h in self.order],
-                                           [self.live[h]["req"].dt for h in self.order],
-                                           flags=nb.NB_BATCH_GRAPH if self.graph else 0)
+        prms = [self.live[h]["prm"] for h in self.order]
+        dts = [self.live[h]["req"].dt for h in self.order]
+        if self.batch is None:
+            self.batch = nb.nbody_batch_create(self.ctx, off, prms, dts,
+                                               flags=nb.NB_BATCH_GRAPH if self.graph else 0)
+            nb.nbody_batch_set_plan(self.ctx, self.batch, self.plan)
+        else:
+            nb.nbody_batch_reset(self.ctx, self.batch, off, prms, dts, stream=self.stream)
         self.pack = pack
         self.dirty = False
-
-    def _retire(self, batch):
-        self.retired.append(batch)
-        if len(self.retired) >= 64:
-            self._free_retired()
-
-    def _free_retired(self):
-        for b in self.retired:
-            self.nb.nbody_batch_destroy(self.ctx, b)
-        self.retired.clear()
 
     def step(self, handles, nsteps):
         if self.dirty:
@@ -306,12 +326,10 @@ class GpuBackend(Backend):
         return {}
 
     def _release(self, handle):
-        # copy the state out of the pack so the pack can be rebuilt without it
         del self.live[handle]
         self.dirty = True
-        if not self.live and self.batch is not None:
-            self._retire(self.batch)
-            self.batch, self.pack = None, None
+        if not self.live:
+            self.pack = None
 
     def finish(self, handle) -> Result:
         nb = self.nb
@@ -333,6 +351,5 @@ class GpuBackend(Backend):
     def close(self):
         self.stream.synchronize()
         if self.batch is not None:
-            self._retire(self.batch)
+            self.nb.nbody_batch_destroy(self.ctx, self.batch)
             self.batch = None
-        self._free_retired()

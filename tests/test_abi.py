@@ -103,6 +103,6 @@ def test_plan_class_constants_match_header():
     text = open(HEADER).read()
     consts = {m.group(1): int(m.group(2), 16) for m in re.finditer(r"#define (NB_PLAN_\w+) (0x[0-9a-fA-F]+)", text)}
     assert consts == {"NB_PLAN_ACCEL": nb.NB_PLAN_ACCEL, "NB_PLAN_POTENTIAL": nb.NB_PLAN_POTENTIAL,
-                      "NB_PLAN_JERK": nb.NB_PLAN_JERK}
+                      "NB_PLAN_JERK": nb.NB_PLAN_JERK, "NB_PLAN_BATCH": nb.NB_PLAN_BATCH}
     assert nb.plan_code("fp64/potential") == nb.NB_FP64 | nb.NB_PLAN_POTENTIAL
     assert nb.plan_code("mixed") == nb.NB_MIXED

@@ -15,9 +15,14 @@ from oracle.metrics import force_errors
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-# mixed: per-pair float32 terms (~10 u) summed over <= 256-source tiles in
-# float32 (<= 255 u of the tile's sum of |f|), tiles added in float64
-MIXED_TOL = {"eps_cond": 2e-5, "eps_rms": 2e-5}
+# mixed: per-pair float32 terms (~10 u, u = 2^-24) summed over <= 256-source
+# tiles in float32 (worst case 255 u = 1.5e-5 of the tile's sum of |f|),
+# tiles added in float64.  Measured at these sizes (N = 300 ... 20000, every
+# plan, far-tile form and mass pattern): eps_cond <= 7.2e-7, eps_rms <=
+# 3.1e-7 (at N = 2^20 both about 5e-8).  Gated at about 3x and 4x of that:
+# float32 running sums (eps_cond ~1e-5 at N = 4099) or a far-tile form that
+# lost its precision fail.
+MIXED_TOL = {"eps_cond": 2e-6, "eps_rms": 1.2e-6}
 # float32 (the paper's SP): float32 positions and a float32 running sum over
 # all N sources; bound ~ (N + 8 |r|/|dr|) u, checked loosely
 FP32_TOL = {"eps_cond": 1e-3}
@@ -49,7 +54,9 @@ def oracle_accel(orc, ic, eps, halo=None, G=1.0):
 
 
 def errs(got, ref, A):
-    return force_errors(np.stack([got["ax"], got["ay"], got["az"]]), ref, A)
+    e = force_errors(np.stack([got["ax"], got["ay"], got["az"]]), ref, A)
+    print(f"[err] {e}", flush=True)
+    return e
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 257, 1021, 4096, 4099])
@@ -107,9 +114,10 @@ def test_potential(nb, ctx, orc, prec):
     ref, phi_ref, A = oracle_accel(orc, ic, 0.01)
     got = run_accel(nb, ctx, ic, 0.01, nb.PREC[prec], phi=True)
     rel = np.max(np.abs(got["phi"] - phi_ref) / np.abs(phi_ref))
+    print(f"[err] potential {prec}: max relative {rel:.2e}", flush=True)
     assert rel <= {"fp64": 1e-13, "mixed": 2e-5, "fp32": 1e-3}[prec], rel
     e = errs(got, ref, A)
-    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec]
+    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": MIXED_TOL["eps_cond"], "fp32": 1e-3}[prec]
 
 
 @pytest.mark.parametrize("prec,eps", [("fp64", 1e-160), ("mixed", 1e-25), ("fp32", 1e-25), ("fp64", 1e-150)])
@@ -123,8 +131,9 @@ def test_tiny_softening(nb, ctx, orc, prec, eps):
     got = run_accel(nb, ctx, ic, eps, nb.PREC[prec], phi=True)
     assert all(np.all(np.isfinite(got[k])) for k in ("ax", "ay", "az", "phi"))
     e = errs(got, ref, A)
-    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec], e
+    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": MIXED_TOL["eps_cond"], "fp32": 1e-3}[prec], e
     rel = np.max(np.abs(got["phi"] - phi_ref) / np.abs(phi_ref))
+    print(f"[err] potential {prec}: max relative {rel:.2e}", flush=True)
     assert rel <= {"fp64": 1e-13, "mixed": 2e-5, "fp32": 1e-3}[prec], rel
 
 
@@ -140,7 +149,9 @@ def test_zero_softening_coincident(nb, ctx, orc, prec):
     got = run_accel(nb, ctx, ic, 0.0, nb.PREC[prec])
     assert all(np.all(np.isfinite(got[k])) for k in ("ax", "ay", "az"))
     e = errs(got, ref, A)
-    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": 2e-5, "fp32": 1e-3}[prec], e
+    assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": MIXED_TOL["eps_cond"], "fp32": 1e-3}[prec], e
+    if prec == "mixed":
+        assert e["eps_rms"] <= MIXED_TOL["eps_rms"], e
 
 
 def test_rows_bitwise(nb, ctx):
@@ -179,7 +190,8 @@ def test_translation_mixed(nb, ctx, orc, jsrc):
     sh["x"] = ic["x"] + 1000.0
     got = run_accel(nb, ctx, sh, 0.01, nb.NB_MIXED, plan=dict(R=2, block=256, split=2, jsrc=jsrc))
     e = errs(got, ref, A)
-    assert e["eps_cond"] <= 2e-5, e
+    for k, v in MIXED_TOL.items():
+        assert e[k] <= v, e
 
 
 def test_empty_and_validation(nb, ctx):
@@ -253,7 +265,7 @@ def test_mixed_tile_local(nb, ctx, orc, plan, model, n):
     # and close to the mixed plans that form every separation in float64
     std = run_accel(nb, ctx, ic, eps, nb.NB_MIXED, halo=halo, plan=dict(R=2, block=256, split=1, jsrc=0))
     e2 = errs(got, np.stack([std["ax"], std["ay"], std["az"]]), A)
-    assert e2["eps_cond"] <= 2e-5, e2
+    assert e2["eps_cond"] <= MIXED_TOL["eps_cond"], e2
 
 
 @pytest.mark.parametrize("jsrc", [2, 3])
@@ -268,12 +280,14 @@ def test_mixed_tile_local_edges(nb, ctx, orc, jsrc):
     ref, _, A = oracle_accel(orc, ic, 0.0)
     got = run_accel(nb, ctx, ic, 0.0, nb.NB_MIXED, plan=plan)
     assert all(np.all(np.isfinite(got[k])) for k in ("ax", "ay", "az"))
-    assert errs(got, ref, A)["eps_cond"] <= MIXED_TOL["eps_cond"]
+    e = errs(got, ref, A)
+    assert e["eps_cond"] <= MIXED_TOL["eps_cond"] and e["eps_rms"] <= MIXED_TOL["eps_rms"], e
     sh = dict(ic)
     sh["x"] = ic["x"] + 1000.0
     ref2, _, A2 = oracle_accel(orc, ic, 0.01)
     got2 = run_accel(nb, ctx, sh, 0.01, nb.NB_MIXED, plan=plan)
-    assert errs(got2, ref2, A2)["eps_cond"] <= MIXED_TOL["eps_cond"]
+    e2 = errs(got2, ref2, A2)
+    assert e2["eps_cond"] <= MIXED_TOL["eps_cond"] and e2["eps_rms"] <= MIXED_TOL["eps_rms"], e2
     # a spatially ordered plan sums whole systems only
     s = nb.System.from_arrays(wl.plummer(2000, 62))
     nb.nbody_plan_set(ctx, nb.NB_MIXED, 2000, plan)

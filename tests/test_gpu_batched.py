@@ -1,9 +1,11 @@
 """Batched persistent launches: many independent systems in one launch.
 
 Each system's result must be bitwise equal to the same system run alone
-under the batch's plan (the plan depends only on the precision), the
-HIP-graph replay must equal eager launches on every replay, and every
-system must match the oracle (float64 gate 1e-12).
+under the single-system plan the batch reports for it (its chunk count and,
+for mixed systems in spatial order, its far-tile form), for several batch
+plans; the HIP-graph replay must equal eager launches on every replay, and
+every system must match the oracle (float64 gate 1e-12, mixed and float32
+their own gates).
 """
 import numpy as np
 import pytest
@@ -62,23 +64,41 @@ def single(nb, ctx, ic, prm, plan, fn):
     return s.numpy()
 
 
-def test_accel_batched_equals_single_and_oracle(nb, ctx, orc):
+# batch plans: R, source tiles per chunk (0: whole systems), jsrc of the mixed systems
+BATCH_PLANS = [None,  # the default plan
+               {"R": 1, "block": 256, "split": 0, "jsrc": 0},
+               {"R": 2, "block": 256, "split": 2, "jsrc": 0},
+               {"R": 1, "block": 256, "split": 3, "jsrc": 3},
+               {"R": 2, "block": 256, "split": 1, "jsrc": 2}]
+
+
+def plan_id(p):
+    return "default" if p is None else f"R{p['R']}s{p['split']}j{p['jsrc']}"
+
+
+@pytest.mark.parametrize("bplan", BATCH_PLANS, ids=plan_id)
+def test_accel_batched_equals_single_and_oracle(nb, ctx, orc, bplan):
+    print(f"[case] batched accel plan {bplan}", flush=True)
     packed, off, parts = make_batch(SPECS)
     prms = [params_of(nb, sp) for sp in SPECS]
     b = nb.nbody_batch_create(ctx, off, prms, [sp[6] for sp in SPECS])
     try:
-        plan = nb.nbody_batch_get_plan(ctx, b)
-        assert plan["split"] == 1
+        if bplan is not None:
+            nb.nbody_batch_set_plan(ctx, b, bplan)
+            assert nb.nbody_batch_get_plan(ctx, b) == bplan
         allsys = nb.System.from_arrays(packed)
         nb.nbody_accel_batched(ctx, b, allsys)
         torch.cuda.synchronize()
         got = allsys.numpy()
         for k, (sp, ic, prm) in enumerate(zip(SPECS, parts, prms)):
             lo, hi = off[k], off[k + 1]
+            plan = nb.nbody_batch_system_plan(ctx, b, k)
+            if bplan is not None and sp[1] > 256 * 2 * max(bplan["split"], 1) and sp[4] != "fp32":
+                assert bplan["split"] == 0 or plan["split"] > 1, (k, plan)
             alone = single(nb, ctx, ic, prm, plan, lambda s: nb.nbody_accel(ctx, s, prm))
             for key in ("ax", "ay", "az"):
-                assert np.array_equal(got[key][lo:hi], alone[key]), (k, key)
-            if sp[1] >= 2 and sp[4] == "fp64":
+                assert np.array_equal(got[key][lo:hi], alone[key]), (k, key, plan)
+            if sp[1] >= 2:
                 ax, ay, az, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], 1.0, sp[3], want_scale=True)
                 if sp[5]:
                     h = wl.default_halo()
@@ -87,18 +107,24 @@ def test_accel_batched_equals_single_and_oracle(nb, ctx, orc):
                     A = A + np.sqrt(hx * hx + hy * hy + hz * hz)
                 e = force_errors(np.stack([got["ax"][lo:hi], got["ay"][lo:hi], got["az"][lo:hi]]),
                                  np.stack([ax, ay, az]), A)
-                assert e["eps_rms"] <= 1e-12 and e["eps_cond"] <= 1e-12, (k, e)
+                gate = {"fp64": 1e-12, "mixed": 2e-6, "fp32": 1e-3}[sp[4]]
+                print(f"[err] batched {plan_id(bplan)} system {k} {sp[4]}: {e}", flush=True)
+                assert e["eps_cond"] <= gate, (k, e)
+                if sp[4] == "fp64":
+                    assert e["eps_rms"] <= 1e-12, (k, e)
     finally:
         nb.nbody_batch_destroy(ctx, b)
 
 
+@pytest.mark.parametrize("bplan", [None, BATCH_PLANS[2]], ids=plan_id)
 @pytest.mark.parametrize("scheme", ["kdk", "o4"])
-def test_steps_batched_equal_single(nb, ctx, scheme):
+def test_steps_batched_equal_single(nb, ctx, scheme, bplan):
     packed, off, parts = make_batch(SPECS)
     prms = [params_of(nb, sp) for sp in SPECS]
     b = nb.nbody_batch_create(ctx, off, prms, [sp[6] for sp in SPECS])
     try:
-        plan = nb.nbody_batch_get_plan(ctx, b)
+        if bplan is not None:
+            nb.nbody_batch_set_plan(ctx, b, bplan)
         allsys = nb.System.from_arrays(packed)
         nb.nbody_accel_batched(ctx, b, allsys)
         (nb.nbody_step_kdk_batched if scheme == "kdk" else nb.nbody_step_o4_batched)(ctx, b, allsys, 3)
@@ -112,7 +138,7 @@ def test_steps_batched_equal_single(nb, ctx, scheme):
                 nb.nbody_accel(ctx, s, prm)
                 step(ctx, s, prm, sp[6], 3)
 
-            alone = single(nb, ctx, ic, prm, plan, run)
+            alone = single(nb, ctx, ic, prm, nb.nbody_batch_system_plan(ctx, b, k), run)
             for key in K:
                 assert np.array_equal(got[key][lo:hi], alone[key]), (scheme, k, key)
     finally:
@@ -242,6 +268,17 @@ def test_batch_mix_full_size_sampled(nb, ctx, orc):
             e = force_errors(np.stack([got["ax"][lo:hi][rows], got["ay"][lo:hi][rows], got["az"][lo:hi][rows]]),
                              np.stack([ax, ay, az]), A)
             worst = max(worst, e["eps_cond"])
-        assert worst <= 2e-5, worst
+        print(f"[err] batched mix worst eps_cond {worst:.3e}", flush=True)
+        assert worst <= 2e-6, worst   # measured 6.5e-7
+        # the largest, the smallest and two other systems alone, under the
+        # plan the batch reports for each: bitwise the batch's sums
+        sizes = np.diff(off)
+        for k in (int(np.argmax(sizes)), int(np.argmin(sizes)), 17, 200):
+            lo, hi = int(off[k]), int(off[k + 1])
+            ic = {f: mix[f][lo:hi] for f in wl.FIELDS}
+            alone = single(nb, ctx, ic, prms[k], nb.nbody_batch_system_plan(ctx, b, k),
+                           lambda s, k=k: nb.nbody_accel(ctx, s, prms[k]))
+            for key in ("ax", "ay", "az"):
+                assert np.array_equal(got[key][lo:hi], alone[key]), (k, key)
     finally:
         nb.nbody_batch_destroy(ctx, b)

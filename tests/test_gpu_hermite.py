@@ -2,9 +2,9 @@
 the oracle, through the C ABI.
 
 Gates: float64 a and j within 1e-12 of the oracle in the conditioned
-measure (error over the sum of the terms' magnitudes); mixed 2e-5 and
-float32 1e-3, as the acceleration paths.  Integrated states are compared
-with the oracle's run of the same steps."""
+measure (error over the sum of the terms' magnitudes); mixed 2e-6 (measured
+at these sizes, every plan: at most 5.7e-7 for a and j) and float32 1e-3.
+Integrated states are compared with the oracle's run of the same steps."""
 import math
 
 import numpy as np
@@ -15,12 +15,14 @@ import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "mixed": 2e-5, "fp32": 1e-3}
+TOL = {"fp64": 1e-12, "mixed": 2e-6, "fp32": 1e-3}
 
 
 def cond_err(got, ref, scale):
     d = np.sqrt(sum((g - r) ** 2 for g, r in zip(got, ref)))
-    return float(np.max(d / scale))
+    e = float(np.max(d / scale))
+    print(f"[err] cond {e:.3e}", flush=True)
+    return e
 
 
 def gpu_aj(nb, ctx, ic, prm):

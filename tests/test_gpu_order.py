@@ -131,3 +131,52 @@ def test_capture_refuses_to_grow_scratch(nb, ctx):
         assert ei.value.status == nb.NB_EINVAL and "capture" in str(ei.value)
     finally:
         nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
+
+
+@pytest.mark.parametrize("plan", [{"R": 1, "block": 256, "split": 4, "jsrc": 3},
+                                  {"R": 2, "block": 256, "split": 1, "jsrc": 2}], ids=["R1s4j3", "R2s1j2"])
+def test_order_rows_bitwise(nb, ctx, plan):
+    # the i-split under a spatially ordered plan: ranges of the Morton order
+    # give the full launch's bits for their particles and touch no others;
+    # three ranges cover the system exactly
+    n = 40000
+    print(f"[case] order rows n={n} plan={plan}", flush=True)
+    ic = wl.exp_disk(n, 23)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    nb.nbody_plan_set(ctx, nb.NB_MIXED, n, plan)
+    try:
+        full = nb.System.from_arrays(ic)
+        nb.nbody_accel(ctx, full, prm)
+        perm, _ = nb.nbody_spatial_order(ctx, full)
+        part = nb.System.from_arrays(ic)
+        for k in ("ax", "ay", "az"):
+            part[k].fill_(7.0)
+        k0, k1 = 1000, 23456
+        nb.nbody_accel_order_rows(ctx, part, prm, k0, k1)
+        torch.cuda.synchronize()
+        p = perm.long()
+        inside = torch.zeros(n, dtype=torch.bool, device="cuda")
+        inside[p[k0:k1]] = True
+        for k in ("ax", "ay", "az"):
+            assert torch.equal(part[k][inside], full[k][inside]), k
+            assert torch.all(part[k][~inside] == 7.0), k
+        whole = nb.System.from_arrays(ic)
+        for a, b in ((0, 777), (777, 31000), (31000, n)):
+            nb.nbody_accel_order_rows(ctx, whole, prm, a, b)
+        torch.cuda.synchronize()
+        for k in ("ax", "ay", "az"):
+            assert torch.equal(whole[k], full[k]), k
+        with pytest.raises(nb.NBodyError) as ei:
+            nb.nbody_accel_order_rows(ctx, whole, prm, 5, n + 1)
+        assert ei.value.status == nb.NB_EINVAL
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
+    # a plan that is not spatially ordered has no such order
+    nb.nbody_plan_set(ctx, nb.NB_MIXED, n, {"R": 1, "block": 256, "split": 1, "jsrc": 0})
+    try:
+        with pytest.raises(nb.NBodyError) as ei:
+            nb.nbody_accel_order_rows(ctx, nb.System.from_arrays(ic), prm, 0, 10)
+        assert ei.value.status == nb.NB_ENOTSUP
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)

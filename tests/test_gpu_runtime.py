@@ -153,7 +153,9 @@ def test_plan_classes(nb, ctx, orc):
     for bad_code, bad in ((jerk, {"R": 2, "block": 256, "split": 1, "jsrc": 1}),
                           (jerk, {"R": 4, "block": 256, "split": 1, "jsrc": 0}),
                           (pot, {"R": 2, "block": 128, "split": 1, "jsrc": 0}),
-                          (nb.NB_FP64 | 0x300, {"R": 1, "block": 256, "split": 1, "jsrc": 0}),
+                          (nb.NB_FP64 | 0x400, {"R": 1, "block": 256, "split": 1, "jsrc": 0}),
+                          (nb.NB_MIXED | nb.NB_PLAN_BATCH, {"R": 4, "block": 256, "split": 1, "jsrc": 0}),
+                          (nb.NB_MIXED | nb.NB_PLAN_BATCH, {"R": 1, "block": 256, "split": 1, "jsrc": 1}),
                           # spatially ordered plans: mixed accelerations only, 256 lanes, R 1 or 2
                           (nb.NB_FP64, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
                           (nb.NB_FP32, {"R": 1, "block": 256, "split": 1, "jsrc": 2}),
@@ -174,9 +176,8 @@ def test_plan_classes(nb, ctx, orc):
 
 
 def test_autotune_with_spatial_plan_pinned(nb, ctx):
-    # a pinned spatially ordered plan sums whole systems only; autotuning its
-    # key still works (above 32768 particles the sweep covers a prefix of the
-    # sources, so the result is a jsrc 0 or 1 plan)
+    # a pinned spatially ordered plan is the first candidate; autotuning its
+    # key times whole systems and pins what it returns
     for n, plan in ((40000, {"R": 1, "block": 256, "split": 4, "jsrc": 3}),
                     (3000, {"R": 2, "block": 256, "split": 2, "jsrc": 2})):
         print(f"[case] autotune n={n} pinned {plan}", flush=True)
@@ -184,7 +185,78 @@ def test_autotune_with_spatial_plan_pinned(nb, ctx):
         try:
             tuned = nb.nbody_autotune(ctx, nb.NB_MIXED, n, 50.0)
             assert nb.nbody_plan_get(ctx, nb.NB_MIXED, n) == tuned
-            if n > 32768:
-                assert tuned["jsrc"] in (0, 1), tuned
         finally:
             nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
+
+
+def _rate(nb, ctx, s, prm, plan, reps=6):
+    nb.nbody_plan_set(ctx, prm.prec, s.n, plan)
+    nb.nbody_accel(ctx, s, prm)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        nb.nbody_accel(ctx, s, prm)
+    b.record()
+    torch.cuda.synchronize()
+    return reps * float(s.n) ** 2 / (a.elapsed_time(b) * 1e-3)
+
+
+def test_autotune_finds_the_headline_plan_class(nb, ctx, orc):
+    # tuning the N = 2^17 disk from the heuristic plan, over every candidate
+    # on the whole system: the result sums in spatial order, matches the
+    # oracle, and is within 3% of the committed plan's rate
+    from oracle.metrics import force_errors
+    n = 1 << 17
+    print(f"[case] autotune mixed disk n={n}", flush=True)
+    ic = wl.exp_disk(n, 2)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    committed = nb.read_plans()["mixed"]["17"]
+    s = nb.System.from_arrays(ic)
+    nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
+    try:
+        tuned = nb.nbody_autotune_sys(ctx, nb.NB_MIXED, s, prm, 0.0)
+        print(f"[tune] 2^17 mixed: tuned {tuned}, committed {committed}", flush=True)
+        assert tuned["jsrc"] in (2, 3), tuned
+        assert nb.nbody_plan_get(ctx, nb.NB_MIXED, n) == tuned
+        rows = np.sort(np.random.default_rng(8).choice(n, size=512, replace=False))
+        ax, ay, az, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], 1.0, 0.02, rows=rows, want_scale=True)
+        hx, hy, hz = orc.halo_accel(ic["x"][rows], ic["y"][rows], ic["z"][rows], orc.Halo(h.v2, h.rc))
+        A = A + np.sqrt(hx * hx + hy * hy + hz * hz)
+        rt = torch.as_tensor(rows, device="cuda")
+        got = torch.stack([s[k][rt] for k in ("ax", "ay", "az")]).cpu().numpy()
+        e = force_errors(got, np.stack([ax + hx, ay + hy, az + hz]), A)
+        assert e["eps_cond"] <= 2e-7 and e["eps_rms"] <= 2e-7, e
+        r_tuned = max(_rate(nb, ctx, s, prm, tuned) for _ in range(2))
+        r_comm = max(_rate(nb, ctx, s, prm, committed) for _ in range(2))
+        print(f"[tune] rates tuned {r_tuned:.4e} committed {r_comm:.4e}", flush=True)
+        assert r_tuned >= 0.97 * r_comm, (tuned, r_tuned, committed, r_comm)
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
+
+
+def test_batch_autotune(nb, ctx):
+    # the batch tuner times batch plans on the caller's state and sets and
+    # pins the fastest; the batch then runs under it
+    mix = wl.batch_mix(32, 5)
+    off = mix["off"]
+    B = len(off) - 1
+    h = wl.default_halo()
+    prms = [nb.Params(eps=0.01 if mix["kind"][k] == "plummer" else 0.02, prec=nb.NB_MIXED,
+                      halo=mix["kind"][k] == "disk", halo_v2=h.v2, halo_rc=h.rc) for k in range(B)]
+    b = nb.nbody_batch_create(ctx, off, prms, [1e-3] * B)
+    try:
+        s = nb.System.from_arrays(mix)
+        best = nb.nbody_batch_autotune(ctx, b, s, 0.0)
+        print(f"[tune] batch of {B}: {best}", flush=True)
+        assert nb.nbody_batch_get_plan(ctx, b) == best
+        nmax = int(np.diff(off).max())
+        assert nb.nbody_plan_get(ctx, nb.NB_MIXED | nb.NB_PLAN_BATCH, nmax) == best
+        got = {k: s[k].clone() for k in ("ax", "ay", "az")}
+        nb.nbody_accel_batched(ctx, b, s)
+        torch.cuda.synchronize()
+        for k in ("ax", "ay", "az"):
+            assert torch.equal(got[k], s[k]), k
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED | nb.NB_PLAN_BATCH, int(np.diff(off).max()), None)
+        nb.nbody_batch_destroy(ctx, b)

@@ -1,7 +1,7 @@
 """Serving on the GPU: requests that arrive while others run are batched
-together; each result must equal the same request run alone (bitwise: the
-batched plan depends only on the precision) and float64 requests must
-track the oracle."""
+together; each result must equal the same request run alone (bitwise: under
+the loop's batch plan a system's sums depend only on its own size and
+precision) and float64 requests must track the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -55,8 +55,8 @@ def test_mix_equals_alone_and_oracle(nb, ctx, orc):
 
 def test_budget_queueing_on_gpu(nb, ctx):
     reqs = stream()[:6]
-    biggest = max(80 * r.n for r in reqs)
     be = GpuBackend(ctx)
+    biggest = max(be.footprint(r) for r in reqs)
     st = Scheduler(be, hbm_budget=biggest + 1, max_tick_steps=4).run(reqs)
     be.close()
     assert all(r.error is None for r in st.results)

@@ -86,3 +86,33 @@ def test_metric_pins_catch_planted_mistake(tmp_path, name, orig, bad):
                         "tests/test_oracle_metrics.py"], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"
+
+
+EQ_SRC = os.path.join(ROOT, "oracle", "equilibrium.py")
+
+# planted mistakes in the disk-equilibrium reference (oracle/equilibrium.py)
+EQ_MUTATIONS = [
+    ("rho_* sign", "return w, -k4 * (math.exp(u) - rho_star)", "return w, -k4 * (math.exp(u) + rho_star)"),
+    ("4 pi G factor", "k4 = 4.0 * math.pi * G / cz2", "k4 = 2.0 * math.pi * G / cz2"),
+    ("RK4 weights", "u_new = u + h / 6.0 * (a1 + 2.0 * a2 + 2.0 * a3 + a4)",
+     "u_new = u + h / 4.0 * (a1 + a2 + a3 + a4)"),
+    ("column without both sides", "    return 2.0 * s", "    return s"),
+    ("drift term sign", "out.append(vc2[k] + cr2[k] * (1.0 - cphi2[k] / cr2[k] + dlog))",
+     "out.append(vc2[k] + cr2[k] * (1.0 - cphi2[k] / cr2[k] - dlog))"),
+    ("dispersion ratio dropped", "out.append(vc2[k] + cr2[k] * (1.0 - cphi2[k] / cr2[k] + dlog))",
+     "out.append(vc2[k] + cr2[k] * (1.0 + dlog))"),
+    ("log derivative in r", "/ (math.log(r[b]) - math.log(r[a]))", "/ (r[b] - r[a])"),
+]
+
+
+@pytest.mark.parametrize("name,orig,bad", EQ_MUTATIONS, ids=[m[0] for m in EQ_MUTATIONS])
+def test_equilibrium_pins_catch_planted_mistake(tmp_path, name, orig, bad):
+    text = open(EQ_SRC).read()
+    assert text.count(orig) == 1, f"mutation anchor not unique: {name}"
+    src = tmp_path / "equilibrium_mut.py"
+    src.write_text(text.replace(orig, bad))
+    env = dict(os.environ, NBODY_EQUILIBRIUM_SRC=str(src))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_equilibrium.py"], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0, f"no pin caught the planted mistake: {name}\n{r.stdout[-2000:]}"

@@ -7,7 +7,9 @@ NB_PLAN_* classes in include/nbody.h:
     and R 1 or 2;
   * potential pass: 256 lanes, R 1 or 2, jsrc 0 or 1;
   * acceleration-and-jerk sum: 256 lanes, R 1 or 2, jsrc 0, or 2 (spatial
-    order) for mixed.
+    order) for mixed;
+  * batch plans (mixed/batch, keyed by the largest system): 256 lanes, R 1 or
+    2, split = source tiles per chunk >= 0 (0: whole systems), jsrc 0, 2 or 3.
 A bad entry would make load_plans fail on the GPU; this checks the file on
 the host.  Keys are ceil(log2 n) of the size class."""
 import json
@@ -19,6 +21,9 @@ TABLE = os.path.join(ROOT, "paper_1803_01190_amd", "tuned_plans.json")
 
 def _ok(prec: str, cls: str, p: dict) -> bool:
     R, block, split, jsrc = p["R"], p["block"], p["split"], p["jsrc"]
+    if cls == "batch":
+        return (prec == "mixed" and block == 256 and R in (1, 2) and isinstance(split, int)
+                and 0 <= split <= (1 << 20) and jsrc in (0, 2, 3))
     if not (isinstance(split, int) and 1 <= split <= 1024):
         return False
     if cls == "jerk":
@@ -40,7 +45,7 @@ def test_plan_table_entries_valid():
     for key, sizes in table["gfx950"].items():
         prec, _, cls = key.partition("/")
         assert prec in ("fp64", "mixed", "fp32"), key
-        assert cls in ("", "potential", "jerk"), key
+        assert cls in ("", "potential", "jerk", "batch"), key
         for log2n, plan in sizes.items():
             assert 0 <= int(log2n) <= 31, (key, log2n)
             assert set(plan) == {"R", "block", "split", "jsrc"}, (key, log2n, plan)
@@ -76,6 +81,11 @@ def test_plan_rule_rejects_known_bad_plans():
         ("mixed", "jerk", dict(good, jsrc=3)),
         ("fp64", "jerk", dict(good, R=4)),
         ("fp64", "accel", dict(good, split=0)),
+        ("mixed", "batch", dict(good, jsrc=1)),
+        ("mixed", "batch", dict(good, R=4)),
+        ("mixed", "batch", dict(good, block=128)),
+        ("fp64", "batch", good),
     ]
+    assert _ok("mixed", "batch", dict(good, split=0, jsrc=3))
     for prec, cls, p in bad:
         assert not _ok(prec, cls, p), (prec, cls, p)
