@@ -180,6 +180,24 @@ NBODY_API const char *nbody_version(void);
 NBODY_API nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                          void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): nbody_accel with
+ * every piece of library scratch in a static device array of 128 MiB that
+ * the library holds on each GPU until the process ends (no hipMalloc,
+ * hipFree or other allocating call).  The plan is the context's plan for
+ * (prec, n), with its source split halved until the split partial sums fit
+ * beside the spatial order; a split that had to shrink changes the summation
+ * order, so the result then agrees with nbody_accel to rounding, not
+ * bitwise.  Sizes beyond the maximum return NB_EINVAL with a message: a
+ * spatially ordered plan (jsrc 2 or 3) needs about 56 B per particle, so it
+ * is limited to n of about 2.3e6; jsrc 0 and 1 plans with split 1 need no
+ * scratch at all.  Nothing in the array needs to start at zero (every call
+ * overwrites what it reads).  All calls on one GPU share its array: calls
+ * that overlap on the device race, so order them on one stream (or
+ * synchronise).  Same arguments, errors and results otherwise. */
+NBODY_API nbody_status nbody_accel_static(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
+                                          void *stream);
+
 /* Same as nbody_accel for the targets i in [i0, i1) only (all n particles
  * are sources).  Rows [i0, i1) are bitwise equal to those of nbody_accel
  * under the same plan; the other rows are untouched.  This is one GPU's

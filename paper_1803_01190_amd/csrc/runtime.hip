@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -28,6 +29,21 @@
 #include "jerk_local.h"
 
 using namespace nb;
+
+// Device scratch of nbody_accel_static, the entry point for callers that
+// cannot allocate: the spatial order (jsrc 2 and 3 plans) and the split
+// partial sums live here instead of in context-owned allocations.  Each GPU
+// that runs the library holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: nbody_ctx_create resolves each
+// device's copy once (hipGetSymbolAddress, with that device current) and the
+// kernels receive that address.
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> address of its copy of `scratch`
+}  // namespace
 
 struct nbody_ctx {
     int device = 0;
@@ -47,6 +63,7 @@ struct nbody_ctx {
     double *dseg = nullptr;   // per-segment sums of the diagnostics' first pass
     size_t dseg_cap = 0;      // doubles
     SysConst *sysc = nullptr;  // one SysConst for single-system diagnostics
+    void *static_scratch = nullptr;  // this device's copy of `scratch`
     // Scratch outgrown by a larger call is kept (not freed) until the
     // context is destroyed: a HIP graph captured earlier may still use it,
     // and freeing would synchronise the device.
@@ -577,6 +594,23 @@ nbody_status nbody_ctx_create(int device, nbody_ctx **out) {
         delete ctx;
         return NB_ENOMEM;
     }
+    {
+        // once per device, with the device current: the address of its copy
+        // of the static scratch
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        auto it = g_scratch_ptr.find(device);
+        if (it == g_scratch_ptr.end()) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) {
+                (void)hipFree(ctx->sysc);
+                delete ctx;
+                return NB_EHIP;
+            }
+            it = g_scratch_ptr.emplace(device, ptr).first;
+        }
+        ctx->static_scratch = it->second;
+    }
     *out = ctx;
     return NB_OK;
 }
@@ -613,6 +647,38 @@ nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const nbody_param
                         0.0, (hipStream_t)stream);
     } catch (...) {
         return fail(ctx, NB_ENOMEM, "host exception in nbody_accel");
+    }
+}
+
+nbody_status nbody_accel_static(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm, void *stream) {
+    if (!ctx) return NB_EINVAL;
+    try {
+        nbody_status r = check_sys(ctx, sys, false);
+        if (r == NB_OK) r = check_params(ctx, prm);
+        if (r != NB_OK || sys->n == 0) return r;
+        if (!ctx->static_scratch) return fail(ctx, NB_EHIP, "static scratch address not resolved");
+        DevGuard g(ctx->device);
+        const int64_t n = sys->n;
+        const int mode = sys->phi ? MODE_ACC_PHI : MODE_ACC;
+        nbody_plan pl = mode_plan(ctx, prm->prec, n, mode);
+        if (!pair_config_supported(prm->prec, pl.R, pl.block, pl.jsrc, mode))
+            return fail(ctx, NB_ENOTSUP, "unsupported plan R=%d block=%d jsrc=%d for mode %d", pl.R, pl.block,
+                        pl.jsrc, mode);
+        // the order first (256-byte aligned), then the partial sums; the
+        // split is halved until both fit
+        const size_t order_bytes = pl.jsrc >= 2 ? (local_order_bytes(n) + 255) & ~(size_t)255 : 0;
+        auto part_bytes = [&](int split) { return split > 1 ? (size_t)split * 4 * (size_t)n * sizeof(double) : 0; };
+        while (pl.split > 1 && order_bytes + part_bytes(pl.split) > kStaticScratchBytes) pl.split /= 2;
+        if (order_bytes + part_bytes(pl.split) > kStaticScratchBytes)
+            return fail(ctx, NB_EINVAL,
+                        "n = %lld needs %zu bytes of static scratch for its spatially ordered plan; "
+                        "nbody_accel_static holds %zu bytes (use nbody_accel, or pin a jsrc 0 or 1 plan)",
+                        (long long)n, order_bytes, kStaticScratchBytes);
+        PairLaunch P = make_pair_launch(make_state(sys), make_sysconst(prm, 0, n, 0.0), 0, n, mode, pl, 0, 0.0);
+        P.part = pl.split > 1 ? (double *)((char *)ctx->static_scratch + order_bytes) : nullptr;
+        return launch_pair_seq(ctx, P, ctx->static_scratch, (hipStream_t)stream);
+    } catch (...) {
+        return fail(ctx, NB_ENOMEM, "host exception in nbody_accel_static");
     }
 }
 

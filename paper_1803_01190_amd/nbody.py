@@ -73,6 +73,7 @@ def _load():
         "nbody_ctx_destroy": ([P]),
         "nbody_accel": ([P, S, PR, V]),
         "nbody_accel_rows": ([P, S, PR, I64, I64, V]),
+        "nbody_accel_static": ([P, S, PR, V]),
         "nbody_accel_order_rows": ([P, S, PR, I64, I64, V]),
         "nbody_step_kdk": ([P, S, PR, D, I64, V]),
         "nbody_step_o4": ([P, S, PR, D, I64, V]),
@@ -214,6 +215,11 @@ def nbody_accel_order_rows(ctx, sys: System, prm: Params, k0: int, k1: int, stre
     cs, cp = sys.c(), prm.c()
     _check(ctx, _lib.nbody_accel_order_rows(ctx, ctypes.byref(cs), ctypes.byref(cp), int(k0), int(k1),
                                             _stream(stream)))
+
+
+def nbody_accel_static(ctx, sys: System, prm: Params, stream=None):
+    cs, cp = sys.c(), prm.c()
+    _check(ctx, _lib.nbody_accel_static(ctx, ctypes.byref(cs), ctypes.byref(cp), _stream(stream)))
 
 
 def nbody_accel_rows(ctx, sys: System, prm: Params, i0: int, i1: int, stream=None):
