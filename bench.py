@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--long-runs", default="fp64,fp64_alt,mixed,fp32",
                     help="longrun: runs (fp64_alt: float64 with another summation order)")
     ap.add_argument("--out-dir", default="longrun_out", help="longrun: series and maps")
+    ap.add_argument("--long-equilibrium", action="store_true",
+                    help="longrun: start from the disk iterated to equilibrium (Eqs. (3)-(4))")
     ap.add_argument("--stop-at", type=int, default=None,
                     help="longrun: stop each run at this step and save it for --resume-dir")
     ap.add_argument("--resume-dir", default=None, help="longrun: continue the runs saved there")
@@ -125,6 +127,8 @@ def main():
                     help="serving: capacity in requests/s (skip its measurement)")
     ap.add_argument("--serve-out", default=None, help="serving: also write the result JSON here")
     ap.add_argument("--integ-out", default=None, help="integrators: also write the result JSON here")
+    ap.add_argument("--batch-tune-ms", type=float, default=3000.0,
+                    help="batched: autotune the batch plan on the batch first (0: the pinned or default plan)")
     ap.add_argument("--profile-run", action="store_true",
                     help="run for counter collection: no CPU baseline, plus a copy kernel of "
                          "known size to calibrate FETCH_SIZE / WRITE_SIZE")
@@ -213,7 +217,7 @@ def main():
         prof = nb.nbody_profile_read(ctx.h)
         d1 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
         step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
-        if prec == precs[0] and args.steps < MIN_LATENCY_SAMPLES:
+        if prec == precs[0] and args.steps < MIN_LATENCY_SAMPLES and not args.profile_run:
             # more per-step latency samples for p50/p99, after the timed region
             extra = MIN_LATENCY_SAMPLES - args.steps
             ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(extra + 1)]
@@ -358,10 +362,22 @@ def bench_batched(args):
     prms = [nb.Params(eps=0.01 if mix["kind"][k] == "plummer" else 0.02, prec=nb.NB_MIXED,
                       halo=mix["kind"][k] == "disk", halo_v2=h.v2, halo_rc=h.rc) for k in range(B)]
     ctx = nb.Context(0)
+    nb.load_plans(ctx.h)
+    if args.plans_in:
+        nb.load_plans(ctx.h, args.plans_in)
     out = {}
     # persistent + graph
     b = nb.nbody_batch_create(ctx.h, off, prms, [1e-3] * B, flags=nb.NB_BATCH_GRAPH)
     s = nb.System.from_arrays(mix)
+    if args.batch_tune_ms > 0:
+        t0 = time.perf_counter()
+        plan = nb.nbody_batch_autotune(ctx.h, b, s, args.batch_tune_ms)
+        log(f"[bench] batch plan tuned: {plan} ({time.perf_counter() - t0:.1f}s)")
+    plan = nb.nbody_batch_get_plan(ctx.h, b)
+    if args.plans_out:
+        log2 = max(0, int(sizes.max() - 1).bit_length())
+        with open(args.plans_out, "w") as f:
+            json.dump({"gfx950": {"mixed/batch": {str(log2): plan}}}, f, indent=1)
     nb.nbody_accel_batched(ctx.h, b, s)
     nb.nbody_step_kdk_batched(ctx.h, b, s, 1)  # capture + warm-up
     torch.cuda.synchronize()
@@ -375,22 +391,31 @@ def bench_batched(args):
     wall = time.perf_counter() - w0
     lat = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
     out["persistent_graph"] = {"value": steps * inter / wall, "ms_per_step": 1e3 * wall / steps,
-                               "latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)}}
+                               "latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99),
+                                              "samples": len(lat)},
+                               "plan": plan}
+    sys_plans = [nb.nbody_batch_system_plan(ctx.h, b, k) for k in range(B)]
     nb.nbody_batch_destroy(ctx.h, b)
     log(f"[bench] batched persistent+graph: {out['persistent_graph']}")
-    # one launch per system (same plan as the batch: R=1, block=256, split=1)
+    # one launch per system, each under the plan that gives the batch's bits
+    # (so the two modes do the same arithmetic)
     systems = [nb.System.from_arrays({f: mix[f][off[k]:off[k + 1]] for f in wl.FIELDS}) for k in range(B)]
+
+    def per_system_step(k):
+        nb.nbody_plan_set(ctx.h, nb.NB_MIXED, int(sizes[k]), sys_plans[k])
+        nb.nbody_step_kdk(ctx.h, systems[k], prms[k], 1e-3, 1)
+
     for k in range(B):
-        nb.nbody_plan_set(ctx.h, nb.NB_MIXED, int(sizes[k]), {"R": 1, "block": 256, "split": 1, "jsrc": 0})
+        nb.nbody_plan_set(ctx.h, nb.NB_MIXED, int(sizes[k]), sys_plans[k])
         nb.nbody_accel(ctx.h, systems[k], prms[k])
     ps = max(1, steps // 10)
     for k in range(B):
-        nb.nbody_step_kdk(ctx.h, systems[k], prms[k], 1e-3, 1)
+        per_system_step(k)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for _ in range(ps):
         for k in range(B):
-            nb.nbody_step_kdk(ctx.h, systems[k], prms[k], 1e-3, 1)
+            per_system_step(k)
     torch.cuda.synchronize()
     wall1 = time.perf_counter() - w0
     out["one_launch_per_system"] = {"value": ps * inter / wall1, "ms_per_step": 1e3 * wall1 / ps, "steps": ps}
@@ -559,6 +584,12 @@ def bench_longrun(args):
     ic = wl.make("disk_sg", n, seed)
     ctx = nb.Context(0)
     nb.load_plans(ctx.h)
+    if args.long_equilibrium:
+        # the disk iterated to the balance of Eqs. (3)-(4) under its own forces
+        from paper_1803_01190_amd.equilibrium import equilibrium_disk
+        t0 = time.perf_counter()
+        ic = equilibrium_disk(ctx.h, ic, eps=eps, seed=seed)
+        log(f"[longrun] equilibrium initial conditions in {time.perf_counter() - t0:.1f}s")
     grid = lr.Grid(256, 256, -6.0, -6.0, 12.0 / 256)
     maps_at = [steps * k // 10 for k in range(11)]
     alt_plan = {"R": 1, "block": 256, "split": 3, "jsrc": 0}  # a split no tuned plan uses
@@ -630,7 +661,8 @@ def bench_longrun(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[
                "fp64" if head == "fp64_alt" else head], "data": "synthetic",
            "config": {"workload": f"self-gravitating exponential disk N={n} (no halo), eps={eps}, "
-                                  f"KDK dt={dt:.6g} (outer period / 4000), seed {seed}", "n": n},
+                                  f"KDK dt={dt:.6g} (outer period / 4000), seed {seed}"
+                                  + (", iterated to equilibrium" if args.long_equilibrium else ""), "n": n},
            "table2": out, "maps": maps}
     print(json.dumps(res))
     ctx.close()
@@ -682,7 +714,7 @@ def bench_hermite(args):
         prof = nb.nbody_profile_read(ctx.h)
         d1 = nb.diag_dict(nb.nbody_diag(ctx.h, s, prm))
         step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
-        if prec == precs[0] and args.steps < MIN_LATENCY_SAMPLES:
+        if prec == precs[0] and args.steps < MIN_LATENCY_SAMPLES and not args.profile_run:
             # more per-step latency samples for p50/p99, after the timed region
             extra = MIN_LATENCY_SAMPLES - args.steps
             ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(extra + 1)]

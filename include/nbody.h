@@ -347,9 +347,10 @@ NBODY_API nbody_status nbody_batch_reset(nbody_ctx *ctx, nbody_batch *batch, int
  *          in ceil(n / (256 split)) chunks whose partial sums are reduced in
  *          a fixed order (0: whole systems, no chunks; float32 systems never
  *          split);
- *   jsrc   for the NB_MIXED systems: 0 (LDS source tiles) or 2, 3 (the
- *          batch in spatial order, far tiles in the tile-local float32 forms
- *          of the single-system plans with the same jsrc).
+ *   jsrc   for the NB_MIXED systems: 0 (LDS source tiles) or 2, 3 (systems
+ *          of at least 2^15 particles in spatial order, far tiles in the
+ *          tile-local float32 forms of the single-system plans with the same
+ *          jsrc; smaller ones with LDS source tiles).
  * nbody_batch_create takes the plan pinned with class NB_PLAN_BATCH for
  * (NB_MIXED, the batch's largest n), else {1, 256, 32, 3}. */
 NBODY_API nbody_status nbody_batch_get_plan(nbody_ctx *ctx, const nbody_batch *batch, nbody_plan *out);

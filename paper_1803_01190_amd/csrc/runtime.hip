@@ -1000,6 +1000,12 @@ nbody_status nbody_spatial_order(nbody_ctx *ctx, const nbody_sys *sys, int32_t *
 
 // ---- batched ---------------------------------------------------------------
 
+// A batch sums its NB_MIXED systems in spatial order (batch plans with jsrc 2
+// or 3) from this size on; smaller systems have few source tiles far enough
+// from a target tile for the tile-local forms and keep float64-formed
+// separations (LDS tiles).
+constexpr int64_t kLocalMinN = 1 << 15;
+
 static bool batch_plan_supported(const nbody_plan &pl) {
     return pl.block == 256 && (pl.R == 1 || pl.R == 2) && pl.split >= 0 && pl.split <= (1 << 20) &&
            (pl.jsrc == 0 || pl.jsrc == 2 || pl.jsrc == 3);
@@ -1037,7 +1043,7 @@ static nbody_status plan_batch(nbody_ctx *ctx, nbody_batch *bt, const nbody_plan
     for (int32_t b = 0; b < B; ++b) {
         const SysConst &c = bt->sc[b];
         BatchSys &ly = bt->lay[b];
-        ly.local = (c.prec == P_MIXED && pl.jsrc >= 2 && c.n > 0) ? 1 : 0;
+        ly.local = (c.prec == P_MIXED && pl.jsrc >= 2 && c.n >= kLocalMinN) ? 1 : 0;
         int64_t split = 1;
         if (c.prec != P_FP32 && pl.split > 0 && c.n > 0)
             split = std::max<int64_t>(1, (c.n + 256LL * pl.split - 1) / (256LL * pl.split));

@@ -115,7 +115,7 @@ def test_potential(nb, ctx, orc, prec):
     got = run_accel(nb, ctx, ic, 0.01, nb.PREC[prec], phi=True)
     rel = np.max(np.abs(got["phi"] - phi_ref) / np.abs(phi_ref))
     print(f"[err] potential {prec}: max relative {rel:.2e}", flush=True)
-    assert rel <= {"fp64": 1e-13, "mixed": 2e-5, "fp32": 1e-3}[prec], rel
+    assert rel <= {"fp64": 1e-13, "mixed": 2e-6, "fp32": 1e-3}[prec], rel  # mixed measured <= 5.6e-7
     e = errs(got, ref, A)
     assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": MIXED_TOL["eps_cond"], "fp32": 1e-3}[prec]
 
@@ -134,7 +134,7 @@ def test_tiny_softening(nb, ctx, orc, prec, eps):
     assert e["eps_cond"] <= {"fp64": FP64_TOL, "mixed": MIXED_TOL["eps_cond"], "fp32": 1e-3}[prec], e
     rel = np.max(np.abs(got["phi"] - phi_ref) / np.abs(phi_ref))
     print(f"[err] potential {prec}: max relative {rel:.2e}", flush=True)
-    assert rel <= {"fp64": 1e-13, "mixed": 2e-5, "fp32": 1e-3}[prec], rel
+    assert rel <= {"fp64": 1e-13, "mixed": 2e-6, "fp32": 1e-3}[prec], rel  # mixed measured <= 5.6e-7
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])

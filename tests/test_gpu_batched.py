@@ -197,6 +197,112 @@ def test_isolation_and_order(nb, ctx):
         nb.nbody_batch_destroy(ctx, b2)
 
 
+LARGE_SPECS = [
+    ("disk", 40000, 21, 0.02, "mixed", True, 1e-3),
+    ("plummer", 700, 22, 0.01, "mixed", False, 1e-3),
+    ("plummer", 33000, 23, 0.01, "mixed", False, 2e-3),
+    ("disk", 5000, 24, 0.02, "fp64", True, 1e-3),
+    ("plummer", 0, 25, 0.01, "mixed", False, 1e-3),
+    ("disk", 32768, 26, 0.02, "mixed", True, 1e-3),
+]
+
+
+@pytest.mark.parametrize("bplan", [{"R": 1, "block": 256, "split": 16, "jsrc": 3},
+                                   {"R": 2, "block": 256, "split": 0, "jsrc": 2},
+                                   {"R": 1, "block": 256, "split": 7, "jsrc": 2}], ids=plan_id)
+def test_spatial_order_batch_large_systems(nb, ctx, orc, bplan):
+    # mixed systems of 2^15 particles or more are summed in their own spatial
+    # order inside the batch (the smaller ones with LDS tiles): bitwise the
+    # single-system sums under the reported plans, and the oracle's on
+    # sampled rows; one graph-replayed KDK step equals the eager one
+    print(f"[case] batched large systems plan {bplan}", flush=True)
+    packed, off, parts = make_batch(LARGE_SPECS)
+    prms = [params_of(nb, sp) for sp in LARGE_SPECS]
+    dts = [sp[6] for sp in LARGE_SPECS]
+    b = nb.nbody_batch_create(ctx, off, prms, dts, flags=nb.NB_BATCH_GRAPH)
+    try:
+        nb.nbody_batch_set_plan(ctx, b, bplan)
+        allsys = nb.System.from_arrays(packed)
+        nb.nbody_accel_batched(ctx, b, allsys)
+        torch.cuda.synchronize()
+        got = allsys.numpy()
+        rng = np.random.default_rng(9)
+        for k, (sp, ic, prm) in enumerate(zip(LARGE_SPECS, parts, prms)):
+            lo, hi = off[k], off[k + 1]
+            plan = nb.nbody_batch_system_plan(ctx, b, k)
+            if sp[4] == "mixed" and sp[1] >= 1 << 15:
+                assert plan["jsrc"] == bplan["jsrc"], (k, plan)
+            elif sp[1] > 0:
+                assert plan["jsrc"] == 0, (k, plan)
+            alone = single(nb, ctx, ic, prm, plan, lambda s, prm=prm: nb.nbody_accel(ctx, s, prm))
+            for key in ("ax", "ay", "az"):
+                assert np.array_equal(got[key][lo:hi], alone[key]), (k, key, plan)
+            if sp[1] < 2:
+                continue
+            rows = np.sort(rng.choice(sp[1], size=min(256, sp[1]), replace=False))
+            ax, ay, az, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], 1.0, sp[3], rows=rows, want_scale=True)
+            if sp[5]:
+                h = wl.default_halo()
+                hx, hy, hz = orc.halo_accel(ic["x"][rows], ic["y"][rows], ic["z"][rows], orc.Halo(h.v2, h.rc))
+                ax, ay, az = ax + hx, ay + hy, az + hz
+                A = A + np.sqrt(hx * hx + hy * hy + hz * hz)
+            e = force_errors(np.stack([got["ax"][lo:hi][rows], got["ay"][lo:hi][rows], got["az"][lo:hi][rows]]),
+                             np.stack([ax, ay, az]), A)
+            print(f"[err] batched large {plan_id(bplan)} system {k}: {e}", flush=True)
+            gate = {"fp64": 1e-12, "mixed": 2e-6}[sp[4]]
+            assert e["eps_cond"] <= gate and e["eps_rms"] <= gate, (k, e)
+        # graph replay of a step equals the eager step
+        eager = nb.System.from_arrays(got)
+        be = nb.nbody_batch_create(ctx, off, prms, dts)
+        try:
+            nb.nbody_batch_set_plan(ctx, be, bplan)
+            for _ in range(2):
+                nb.nbody_step_kdk_batched(ctx, b, allsys, 1)
+                nb.nbody_step_kdk_batched(ctx, be, eager, 1)
+                torch.cuda.synchronize()
+                for key in K:
+                    assert torch.equal(allsys[key], eager[key]), key
+        finally:
+            nb.nbody_batch_destroy(ctx, be)
+    finally:
+        nb.nbody_batch_destroy(ctx, b)
+
+
+def test_batch_reset_reuses_and_matches_create(nb, ctx):
+    # a batch reset for another set of systems gives the bits of a batch
+    # created for that set, on the stream the reset was ordered on
+    specs_a, specs_b = SPECS, LARGE_SPECS
+    pa, offa, _ = make_batch(specs_a)
+    pb, offb, _ = make_batch(specs_b)
+    prm_a = [params_of(nb, sp) for sp in specs_a]
+    prm_b = [params_of(nb, sp) for sp in specs_b]
+    st = torch.cuda.Stream()
+    b = nb.nbody_batch_create(ctx, offa, prm_a, [sp[6] for sp in specs_a], flags=nb.NB_BATCH_GRAPH)
+    ref = nb.nbody_batch_create(ctx, offb, prm_b, [sp[6] for sp in specs_b])
+    try:
+        sa = nb.System.from_arrays(pa)
+        with torch.cuda.stream(st):
+            nb.nbody_accel_batched(ctx, b, sa, stream=st)
+            nb.nbody_step_kdk_batched(ctx, b, sa, 2, stream=st)
+            nb.nbody_batch_reset(ctx, b, offb, prm_b, [sp[6] for sp in specs_b], stream=st)
+            s1 = nb.System.from_arrays(pb)
+            nb.nbody_accel_batched(ctx, b, s1, stream=st)
+            nb.nbody_step_kdk_batched(ctx, b, s1, 3, stream=st)
+        st.synchronize()
+        assert nb.nbody_batch_get_plan(ctx, b) == nb.nbody_batch_get_plan(ctx, ref)
+        s2 = nb.System.from_arrays(pb)
+        nb.nbody_accel_batched(ctx, ref, s2)
+        nb.nbody_step_kdk_batched(ctx, ref, s2, 3)
+        torch.cuda.synchronize()
+        for key in K:
+            assert torch.equal(s1[key], s2[key]), key
+        with pytest.raises(nb.NBodyError):
+            nb.nbody_batch_reset(ctx, b, [0, 5, 3], prm_b[:2])
+    finally:
+        nb.nbody_batch_destroy(ctx, b)
+        nb.nbody_batch_destroy(ctx, ref)
+
+
 def test_diag_batched(nb, ctx, orc):
     packed, off, parts = make_batch(SPECS)
     prms = [params_of(nb, sp) for sp in SPECS]
