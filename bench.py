@@ -42,6 +42,7 @@ PEAK_CLOCK_HZ = 2.4e9
 MIN_LATENCY_SAMPLES = 50
 DTYPE = {"fp64": "f64", "mixed": "f32 pair / f64 accumulate+state", "fp32": "f32"}
 KERNEL_SOURCES = ["paper_1803_01190_amd/csrc/accel.hip", "paper_1803_01190_amd/csrc/order.hip",
+                  "paper_1803_01190_amd/csrc/halo.h",
                   "paper_1803_01190_amd/csrc/nbody_internal.h"]
 
 

@@ -741,7 +741,7 @@ __global__ __launch_bounds__(256) void k_pair_local(PairLaunch P, int64_t chunk)
 // item does what the single-system kernel's workgroup (blockIdx.x, chunk)
 // does for that system, so a system's sums are bitwise those of a single
 // launch with the same R, split and far-tile form.
-template <int R, bool EXP>
+template <int R, bool SAFE, bool EXP>
 __global__ __launch_bounds__(256) void k_pair_local_batched(BatchLaunch B) {
     constexpr int BLOCK = 256;
     __shared__ JL ftile[BLOCK];
@@ -759,10 +759,8 @@ __global__ __launch_bounds__(256) void k_pair_local_batched(BatchLaunch B) {
         const int64_t je = (jb + ly.chunk < n) ? jb + ly.chunk : n;
         Lane<P_MIXED, R> L;
         lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, BLOCK);
-        if (sc.safe32)
-            local_sweep<R, true, EXP>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile, fmass);
-        else
-            local_sweep<R, false, EXP>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile, fmass);
+        // (the launch holds systems of one masking class: SAFE = sc.safe32)
+        local_sweep<R, SAFE, EXP>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile, fmass);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t i = ib + (int64_t)r * BLOCK + t;
@@ -810,7 +808,7 @@ hipError_t pick_local(const PairLaunch &P, hipStream_t s) {
 // Batched persistent kernel: each workgroup walks the work list with a
 // fixed stride; an item is one tile of BLOCK*R targets of one system
 // against all sources of that system.
-template <int PREC, int R, int BLOCK, int MODE>
+template <int PREC, int R, int BLOCK, int MODE, bool SAFE>
 __global__ __launch_bounds__(BLOCK) void k_pair_batched(BatchLaunch B) {
     __shared__ typename Tr<PREC>::J tile[BLOCK];
     for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
@@ -831,11 +829,9 @@ __global__ __launch_bounds__(BLOCK) void k_pair_batched(BatchLaunch B) {
         }
         Lane<PREC, R> L;
         lane_init<PREC, R>(L, B.st, ib, ilim, BLOCK);
-        const bool safe = (PREC == P_FP64) ? sc.safe64 : sc.safe32;
-        if (safe)
-            sweep_lds<PREC, R, BLOCK, MODE, true>(L, B.st, jb, je, ib, sc.eps2, sc.eps2f, tile);
-        else
-            sweep_lds<PREC, R, BLOCK, MODE, false>(L, B.st, jb, je, ib, sc.eps2, sc.eps2f, tile);
+        // (the launch holds systems of one masking class: SAFE = safe64 for
+        // float64, safe32 otherwise)
+        sweep_lds<PREC, R, BLOCK, MODE, SAFE>(L, B.st, jb, je, ib, sc.eps2, sc.eps2f, tile);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t i = ib + (int64_t)r * BLOCK + threadIdx.x;
@@ -960,7 +956,10 @@ hipError_t reduce_mode(const PairLaunch &P, hipStream_t s) {
 template <int PREC, int R, int BLOCK, int MODE>
 hipError_t go_batched(const BatchLaunch &B, hipStream_t s) {
     if (B.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pair_batched<PREC, R, BLOCK, MODE>), dim3((unsigned)B.grid), dim3(BLOCK), 0, s, B);
+    if (B.safe)
+        hipLaunchKernelGGL((k_pair_batched<PREC, R, BLOCK, MODE, true>), dim3((unsigned)B.grid), dim3(BLOCK), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_pair_batched<PREC, R, BLOCK, MODE, false>), dim3((unsigned)B.grid), dim3(BLOCK), 0, s, B);
     return hipGetLastError();
 }
 
@@ -979,14 +978,17 @@ hipError_t batched_prec(const BatchLaunch &B, hipStream_t s) {
 template <int R, bool EXP>
 hipError_t go_local_batched(const BatchLaunch &B, hipStream_t s) {
     if (B.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pair_local_batched<R, EXP>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
+    if (B.safe)
+        hipLaunchKernelGGL((k_pair_local_batched<R, true, EXP>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_pair_local_batched<R, false, EXP>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
     return hipGetLastError();
 }
 
 template <int R, bool EXP>
 int occ_local() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_local_batched<R, EXP>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_local_batched<R, false, EXP>, 256, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -994,7 +996,8 @@ int occ_local() {
 template <int PREC, int R, int MODE>
 int occ_of() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_batched<PREC, R, 256, MODE>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_batched<PREC, R, 256, MODE, false>, 256, 0) !=
+        hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }

@@ -19,8 +19,10 @@ __device__ __forceinline__ double halo_series_over_s2(double s2) {
     return acc;
 }
 
-// G M(<r) / r^3 at squared radius r2
-__device__ __forceinline__ double halo_g_over_r3(double r2, double v2, double rc) {
+// G M(<r) / r^3 at squared radius r2.  Not inlined: its ~60 float64
+// constants would otherwise be hoisted out of the persistent kernels' item
+// loops and held in registers for the whole loop.
+__device__ __noinline__ double halo_g_over_r3(double r2, double v2, double rc) {
     const double r = sqrt(r2);
     const double s = r / rc;
     if (s < 0.5) return v2 / (rc * rc) * halo_series_over_s2(s * s);

@@ -87,6 +87,8 @@ struct BatchLaunch {
     int32_t prec, mode, R, block;
     int32_t grid;             // persistent workgroups
     double kick_scale;        // closing half kick v += kick_scale * dt_sys * a (0: none)
+    int32_t safe;             // the items' systems need the masked pair term (the SysConst
+                              // safe64 flag for float64 launches, safe32 otherwise)
     const BatchSys *lay;      // device, one per system (NULL: whole systems, no split)
     double *part;             // split partial sums of all systems
     LocalOrder lo;            // the batch's spatial order (systems summed in it)

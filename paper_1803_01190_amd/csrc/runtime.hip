@@ -90,7 +90,7 @@ struct nbody_batch {
     // kernels (or graphs) enqueued earlier may still read it.  Tables are
     // uploaded from pinned host staging memory with stream-ordered copies.
     struct Buf { void *p = nullptr; size_t cap = 0; };
-    Buf b_off, b_sc, b_lay, b_tbase, b_seg, b_items[4], b_all, b_part, b_order;
+    Buf b_off, b_sc, b_lay, b_tbase, b_seg, b_items[8], b_all[2], b_part, b_order;
     int64_t nseg = 0;   // segments of the diagnostics' first pass (b_seg: B + 1 offsets)
     std::vector<void *> retired;
     std::vector<hipGraphExec_t> old_graphs;   // replaced graphs, destroyed with the batch
@@ -109,14 +109,17 @@ struct nbody_batch {
     void *order = nullptr;          // the batch's spatial order
     int any_local = 0, any_split = 0;
     // work lists: [0..2] per precision (LDS source tiles), [3] NB_MIXED
-    // systems in spatial order; one more (all systems, float64, whole
-    // systems) for the potential pass of the diagnostics
-    WorkItem *items[4] = {nullptr, nullptr, nullptr, nullptr};
-    int32_t nitems[4] = {0, 0, 0, 0};
-    int32_t grid[4] = {0, 0, 0, 0};   // persistent workgroups per list
-    WorkItem *items_all = nullptr;
-    int32_t nitems_all = 0;
-    int32_t grid_all = 0;
+    // systems in spatial order, [4..7] the same for systems that need the
+    // masked pair term (a softening whose square is not normal); two more
+    // (all systems, float64, whole systems; unmasked and masked) for the
+    // potential pass of the diagnostics.  Each list is one launch of a kernel
+    // compiled for its masking class.
+    WorkItem *items[8] = {};
+    int32_t nitems[8] = {};
+    int32_t grid[8] = {};   // persistent workgroups per list
+    WorkItem *items_all[2] = {};
+    int32_t nitems_all[2] = {};
+    int32_t grid_all[2] = {};
     // graph cache: key = state pointers + scheme
     struct Graph { State st; int scheme; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
@@ -431,13 +434,15 @@ nbody_status batch_pair(nbody_ctx *ctx, nbody_batch *b, const State &st, double 
             launch_batch_order(st, b->off_dev, b->tbase_dev, b->B, b->ntot, b->ntiles, b->order, &L.lo, s);
         if (e != hipSuccess) return hipfail(ctx, e, "batched spatial order");
     }
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < 8; ++p) {
         if (b->nitems[p] == 0) continue;
         L.items = b->items[p];
         L.nitems = b->nitems[p];
         L.grid = b->grid[p];
-        L.prec = p == 3 ? P_MIXED : p;
-        const hipError_t e = p == 3 ? launch_pair_local_batched(L, b->plan.jsrc, s) : launch_pair_batched(L, s);
+        L.safe = p >= 4;
+        const int kind = p % 4;
+        L.prec = kind == 3 ? P_MIXED : kind;
+        const hipError_t e = kind == 3 ? launch_pair_local_batched(L, b->plan.jsrc, s) : launch_pair_batched(L, s);
         if (e != hipSuccess) return hipfail(ctx, e, "batched pair-sum launch");
     }
     if (b->any_split) {
@@ -1067,14 +1072,15 @@ static nbody_status plan_batch(nbody_ctx *ctx, nbody_batch *bt, const nbody_plan
     std::vector<int32_t> order(B);
     for (int32_t b = 0; b < B; ++b) order[b] = b;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return bt->sc[a].n > bt->sc[c].n; });
-    std::vector<WorkItem> lists[4], all;
+    std::vector<WorkItem> lists[8], all[2];
     for (int32_t b : order) {
         const SysConst &c = bt->sc[b];
         const BatchSys &ly = bt->lay[b];
-        const int li = ly.local ? 3 : c.prec;
+        const int safe = c.prec == P_FP64 ? c.safe64 : c.safe32;
+        const int li = (ly.local ? 3 : c.prec) + 4 * safe;
         for (int32_t k = 0; k < ly.split; ++k)
             for (int64_t i = 0; i < c.n; i += per) lists[li].push_back({b, k, i});
-        for (int64_t i = 0; i < c.n; i += 256) all.push_back({b, 0, i});
+        for (int64_t i = 0; i < c.n; i += 256) all[c.safe64 ? 1 : 0].push_back({b, 0, i});
     }
     // host tables -> one pinned staging area -> device, in stream order
     struct Up { nbody_batch::Buf *dst; const void *src; size_t bytes; };
@@ -1083,8 +1089,9 @@ static nbody_status plan_batch(nbody_ctx *ctx, nbody_batch *bt, const nbody_plan
                         {&bt->b_lay, bt->lay.data(), sizeof(BatchSys) * B},
                         {&bt->b_tbase, tbase.data(), sizeof(int64_t) * (B + 1)},
                         {&bt->b_seg, segbase.data(), sizeof(int64_t) * (B + 1)},
-                        {&bt->b_all, all.data(), sizeof(WorkItem) * all.size()}};
-    for (int p = 0; p < 4; ++p) ups.push_back({&bt->b_items[p], lists[p].data(), sizeof(WorkItem) * lists[p].size()});
+                        {&bt->b_all[0], all[0].data(), sizeof(WorkItem) * all[0].size()},
+                        {&bt->b_all[1], all[1].data(), sizeof(WorkItem) * all[1].size()}};
+    for (int p = 0; p < 8; ++p) ups.push_back({&bt->b_items[p], lists[p].data(), sizeof(WorkItem) * lists[p].size()});
     size_t total = 0;
     for (const Up &u : ups) total += (u.bytes + 255) & ~(size_t)255;
     if (bt->staged) HIPCHECK(ctx, hipEventSynchronize(bt->staged));  // the staging area is free again
@@ -1115,15 +1122,20 @@ static nbody_status plan_batch(nbody_ctx *ctx, nbody_batch *bt, const nbody_plan
     bt->tbase_dev = (int64_t *)bt->b_tbase.p;
     bt->part = (double *)bt->b_part.p;
     bt->order = bt->any_local ? bt->b_order.p : nullptr;
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < 8; ++p) {
         bt->items[p] = (WorkItem *)bt->b_items[p].p;
         bt->nitems[p] = (int32_t)lists[p].size();
-        const int occ = p == 3 ? pair_local_batched_occupancy(pl.R, pl.jsrc) : pair_batched_occupancy(p, pl.R, 256, MODE_ACC);
+        const int kind = p % 4;
+        const int occ = kind == 3 ? pair_local_batched_occupancy(pl.R, pl.jsrc)
+                                  : pair_batched_occupancy(kind, pl.R, 256, MODE_ACC);
         bt->grid[p] = std::min<int32_t>(bt->nitems[p], occ * ctx->cus);
     }
-    bt->items_all = (WorkItem *)bt->b_all.p;
-    bt->nitems_all = (int32_t)all.size();
-    bt->grid_all = std::min<int32_t>(bt->nitems_all, pair_batched_occupancy(P_FP64, 1, 256, MODE_PHI) * ctx->cus);
+    for (int q = 0; q < 2; ++q) {
+        bt->items_all[q] = (WorkItem *)bt->b_all[q].p;
+        bt->nitems_all[q] = (int32_t)all[q].size();
+        bt->grid_all[q] =
+            std::min<int32_t>(bt->nitems_all[q], pair_batched_occupancy(P_FP64, 1, 256, MODE_PHI) * ctx->cus);
+    }
     if (blocking) HIPCHECK(ctx, hipStreamSynchronize(stream));
     return NB_OK;
 }
@@ -1190,7 +1202,8 @@ nbody_status nbody_batch_destroy(nbody_ctx *ctx, nbody_batch *b) {
     destroy_graphs(b);
     for (hipGraphExec_t x : b->old_graphs) (void)hipGraphExecDestroy(x);
     for (nbody_batch::Buf *q : {&b->b_off, &b->b_sc, &b->b_lay, &b->b_tbase, &b->b_seg, &b->b_items[0], &b->b_items[1],
-                                &b->b_items[2], &b->b_items[3], &b->b_all, &b->b_part, &b->b_order})
+                                &b->b_items[2], &b->b_items[3], &b->b_items[4], &b->b_items[5], &b->b_items[6],
+                                &b->b_items[7], &b->b_all[0], &b->b_all[1], &b->b_part, &b->b_order})
         if (q->p) (void)hipFree(q->p);
     for (void *q : b->retired) (void)hipFree(q);
     if (b->stage) (void)hipHostFree(b->stage);
@@ -1316,17 +1329,19 @@ nbody_status nbody_diag_batched(nbody_ctx *ctx, nbody_batch *b, const nbody_sys 
         if (r != NB_OK) return r;
         State st = make_state(all);
         st.phi = ctx->phi;
-        if (b->nitems_all > 0) {
+        for (int q = 0; q < 2; ++q) {
+            if (b->nitems_all[q] == 0) continue;
             BatchLaunch L{};
             L.st = st;
             L.sys = b->sc_dev;
-            L.items = b->items_all;
-            L.nitems = b->nitems_all;
+            L.items = b->items_all[q];
+            L.nitems = b->nitems_all[q];
             L.prec = P_FP64;
             L.mode = MODE_PHI;
             L.R = 1;
             L.block = 256;
-            L.grid = b->grid_all;
+            L.grid = b->grid_all[q];
+            L.safe = q;
             L.kick_scale = 0.0;
             hipError_t e = launch_pair_batched(L, s);
             if (e != hipSuccess) return hipfail(ctx, e, "batched potential launch");

@@ -37,6 +37,8 @@ def main(argv=None) -> int:
     ap.add_argument("--budget-ms", type=float, default=0.0, help="per key (0: every candidate)")
     ap.add_argument("--out", default=nb.TUNED_PLANS)
     ap.add_argument("--merge", action="store_true", help="keep the file's entries that are not re-tuned")
+    ap.add_argument("--start", default=None,
+                    help="plan cache whose plans are pinned first (each key's first candidate)")
     ap.add_argument("--arch", default="gfx950")
     args = ap.parse_args(argv)
     assert torch.cuda.is_available(), "tuning needs the GPU"
@@ -44,6 +46,9 @@ def main(argv=None) -> int:
     table = nb.read_plans(args.out, args.arch) if args.merge else {}
     h = wl.default_halo()
     ctx = nb.Context(0)
+    if args.start:
+        # each key's plan in this cache is its first candidate
+        nb.load_plans(ctx.h, args.start, args.arch)
     try:
         for log2n in _range(args.log2n):
             n = 1 << log2n
