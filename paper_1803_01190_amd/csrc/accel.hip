@@ -23,6 +23,7 @@
 //  * small systems split the sources into `split` chunks whose partial sums
 //    are reduced afterwards in a fixed order (deterministic, no atomics).
 // There is no MFMA: the pair term is not a dense contraction.
+#include <cfloat>
 #include <type_traits>
 
 #include "nbody_internal.h"
@@ -579,6 +580,7 @@ __device__ __forceinline__ void interact_local(Lane<P_MIXED, R> &L, const JL &e,
 struct LocalSys {
     const double *px, *py, *pz, *pm, *tbox;
     int64_t n;
+    const double *qbox;  // quarter-tile boxes (jsrc = 4)
 };
 
 __device__ __forceinline__ State sorted_state(const LocalSys &O) {
@@ -778,6 +780,194 @@ __global__ __launch_bounds__(256) void k_pair_local_batched(BatchLaunch B) {
     }
 }
 
+// Quarter-tile form (jsrc = 4).  The far test is made per wave and per
+// quarter of the source tile (64 sorted sources, one wave's share of the tile
+// load): the box of the wave's targets (its R groups of 64 sorted targets)
+// against each quarter's box.  A quarter farther from that box than its own
+// diagonal takes the subtracted tile-local form with coordinates relative to
+// the quarter's centre (the bound of that form holds with the quarter's
+// diagonal); the other quarters form their separations in float64.  Both
+// forms add s (x_j - x_i) into the same float32 tile sums, so the tile is
+// flushed once, and both are staged in LDS by every tile load.  Quarters are
+// smaller than tiles and one wave's targets span less than a workgroup's, so
+// more of the sum takes the cheap form where tiles are not small against
+// their distances (systems of a few thousand particles, three-dimensional
+// ones).  An equal-mass tile (block vote on the float64 masses) leaves the
+// mass out of both pair terms and applies the float64 mass at the flush.
+template <int R, bool SAFE>
+__device__ __forceinline__ void quarter_sweep(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t ib, int64_t jb,
+                                              int64_t je, double eps2, float eps2f, JL *ftile, JM *dtile) {
+    constexpr int BLOCK = 256;
+    const int t = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index (uniform)
+    const int64_t nq = (O.n + 63) / 64;
+    // box of this wave's targets: quarters ib / 64 + 4 r + w
+    double bmin[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, bmax[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = ib / 64 + 4 * r + w;
+        if (q < nq) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bmin[c] = fmin(bmin[c], O.qbox[6 * q + c]);
+                bmax[c] = fmax(bmax[c], O.qbox[6 * q + 3 + c]);
+            }
+        }
+    }
+    for (int64_t jt = jb; jt < je; jt += BLOCK) {
+        const int64_t q0 = jt / 64;  // first quarter of the tile
+        // lane l tests quarter l % 4 (empty quarters, boxes (DBL_MAX, -DBL_MAX),
+        // test near); bit q of farq: quarter q is far from this wave's targets
+        bool far = false;
+        {
+            const double *qb = O.qbox + 6 * (q0 + (t & 3));
+            double gap2 = 0.0, diag2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double lo = qb[c], hi = qb[3 + c];
+                const double g = fmax(0.0, fmax(lo - bmax[c], bmin[c] - hi));
+                gap2 += g * g;
+                diag2 += (hi - lo) * (hi - lo);
+            }
+            far = gap2 > diag2;
+        }
+        const uint32_t farq = (uint32_t)(__ballot(far) & 0xFull);
+        // stage source j in both forms: float64 (near quarters) and relative
+        // to the centre of its quarter (w) in float32 (far quarters)
+        const int64_t j = jt + t;
+        const bool ok = j < je;
+        const double xj = ok ? O.px[j] : 0.0, yj = ok ? O.py[j] : 0.0, zj = ok ? O.pz[j] : 0.0;
+        const double mj = ok ? O.pm[j] : 0.0;
+        {
+            const double *cq = O.qbox + 6 * (q0 + w);
+            JL e;
+            e.x = ok ? (float)(xj - 0.5 * (cq[0] + cq[3])) : 0.0f;
+            e.y = ok ? (float)(yj - 0.5 * (cq[1] + cq[4])) : 0.0f;
+            e.z = ok ? (float)(zj - 0.5 * (cq[2] + cq[5])) : 0.0f;
+            e.m = (float)mj;
+            ftile[t] = e;
+            JM d;
+            d.x = xj; d.y = yj; d.z = zj; d.m = (float)mj; d.pad = 0.0f;
+            dtile[t] = d;
+        }
+        const double m0 = O.pm[jt];
+        const bool um = __syncthreads_and(mj == m0) != 0;  // also the barrier after the stores
+#pragma unroll 1
+        for (int qd = 0; qd < 4; ++qd) {
+            const JL *fq = ftile + 64 * qd;
+            const JM *dq = dtile + 64 * qd;
+            if ((farq >> qd) & 1u) {
+                const double *cq = O.qbox + 6 * (q0 + qd);
+                const double cx = 0.5 * (cq[0] + cq[3]), cy = 0.5 * (cq[1] + cq[4]), cz = 0.5 * (cq[2] + cq[5]);
+                float rx[R], ry[R], rz[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    rx[r] = (float)(L.xi[r] - cx);
+                    ry[r] = (float)(L.yi[r] - cy);
+                    rz[r] = (float)(L.zi[r] - cz);
+                }
+                if (um) {
+#pragma unroll 4
+                    for (int k = 0; k < 64; ++k) interact_local<R, SAFE, true>(L, fq[k], rx, ry, rz, eps2f);
+                } else {
+#pragma unroll 4
+                    for (int k = 0; k < 64; ++k) interact_local<R, SAFE, false>(L, fq[k], rx, ry, rz, eps2f);
+                }
+            } else if (um) {
+#pragma unroll 4
+                for (int k = 0; k < 64; ++k) {
+                    const JM &f = dq[k];
+                    interact<P_MIXED, R, MODE_ACC, SAFE, true>(L, f.x, f.y, f.z, 0, 0, 0, 0, 0, eps2, eps2f);
+                }
+            } else {
+#pragma unroll 4
+                for (int k = 0; k < 64; ++k) interact_src<P_MIXED, R, MODE_ACC, SAFE>(L, dq[k], eps2, eps2f);
+            }
+        }
+        flush(L, um, m0);
+        __syncthreads();
+    }
+}
+
+// Rows of a spatially ordered launch: the raw sums of target i (a sorted
+// position) go to the split partials of chunk c, or are finished into the
+// particle perm[i].
+template <int R>
+__device__ __forceinline__ void local_rows(const Lane<P_MIXED, R> &L, int64_t ib, int64_t i0, int64_t i1,
+                                           int32_t split, int64_t chunk_index, double *part, const int32_t *perm,
+                                           const State &st, const SysConst &sc, int kick, double hdt) {
+    const int64_t rows = i1 - i0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = ib + (int64_t)r * 256 + threadIdx.x;
+        if (i < i0 || i >= i1) continue;
+        double sx, sy, sz, sp;
+        raw<P_MIXED, R>(L, r, sx, sy, sz, sp);
+        if (split > 1) {
+            double *q = part + chunk_index * 4 * rows + (i - i0);
+            q[0] = sx; q[rows] = sy; q[2 * rows] = sz; q[3 * rows] = sp;
+        } else {
+            finish<P_MIXED, MODE_ACC>(st, sc, perm[i], sx, sy, sz, sp, kick, hdt);
+        }
+    }
+}
+
+// Single system, jsrc = 4: the launch shape of k_pair_local.
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_quarter(PairLaunch P, int64_t chunk) {
+    __shared__ JL ftile[256];
+    __shared__ JM dtile[256];
+    const int64_t n = P.sc.n;
+    const LocalSys O{P.lo.px, P.lo.py, P.lo.pz, P.lo.pm, P.lo.tbox, n, P.lo.qbox};
+    const int64_t ib = (P.i0 / (256 * R) + (int64_t)blockIdx.x) * (256 * R);
+    const int64_t jb = (int64_t)blockIdx.y * chunk;
+    const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+    Lane<P_MIXED, R> L;
+    lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, 256);
+    quarter_sweep<R, SAFE>(L, O, ib, jb, je, P.sc.eps2, P.sc.eps2f, ftile, dtile);
+    local_rows<R>(L, ib, P.i0, P.i1, P.split, blockIdx.y, P.part, P.lo.perm, P.st, P.sc, P.kick, P.hdt);
+}
+
+// Batched, jsrc = 4: the items of k_pair_local_batched.
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_quarter_batched(BatchLaunch B) {
+    __shared__ JL ftile[256];
+    __shared__ JM dtile[256];
+    for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
+        const WorkItem it = B.items[w];
+        const SysConst sc = B.sys[it.sys];
+        const BatchSys ly = B.lay[it.sys];
+        const int64_t n = sc.n, off = sc.off;
+        const LocalSys O{B.lo.px + off, B.lo.py + off, B.lo.pz + off, B.lo.pm + off, B.lo.tbox + 6 * ly.tbase, n,
+                         B.lo.qbox + 24 * ly.tbase};
+        const int64_t ib = it.i0;
+        const int64_t jb = (int64_t)it.chunk * ly.chunk;
+        const int64_t je = (jb + ly.chunk < n) ? jb + ly.chunk : n;
+        Lane<P_MIXED, R> L;
+        lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, 256);
+        quarter_sweep<R, SAFE>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile);
+        // split partials are [split][4][n] from pbase; rows are the system's sorted positions
+        local_rows<R>(L, ib, 0, n, ly.split, it.chunk, B.part + ly.pbase, B.lo.perm + off, B.st, sc,
+                      B.kick_scale != 0.0, 0.5 * B.kick_scale * sc.dt);
+    }
+}
+
+template <int R>
+hipError_t go_quarter(const PairLaunch &P, hipStream_t s) {
+    const int64_t n = P.sc.n;
+    const int64_t per = 256LL * R;
+    const int64_t nbx = (P.i1 - (P.i0 / per) * per + per - 1) / per;
+    const int64_t per_chunk = (n + P.split - 1) / P.split;
+    const int64_t chunk = ((per_chunk + 255) / 256) * 256;
+    if (nbx <= 0) return hipSuccess;
+    dim3 grid((unsigned)nbx, (unsigned)P.split);
+    if (P.sc.safe32)
+        hipLaunchKernelGGL((k_pair_quarter<R, true>), grid, dim3(256), 0, s, P, chunk);
+    else
+        hipLaunchKernelGGL((k_pair_quarter<R, false>), grid, dim3(256), 0, s, P, chunk);
+    return hipGetLastError();
+}
+
 template <int R, bool EXP>
 hipError_t go_local(const PairLaunch &P, hipStream_t s) {
     const int64_t n = P.sc.n;
@@ -798,6 +988,7 @@ hipError_t pick_local(const PairLaunch &P, hipStream_t s) {
     if (P.sc.prec != P_MIXED || P.mode != MODE_ACC || P.block != 256 || P.i0 < 0 || P.i1 > P.sc.n ||
         P.i1 <= P.i0 || !P.lo.perm)
         return hipErrorInvalidValue;
+    if (P.jsrc == 4) return P.R == 1 ? go_quarter<1>(P, s) : (P.R == 2 ? go_quarter<2>(P, s) : hipErrorInvalidValue);
     const bool exp = P.jsrc == 3;
     if (P.R == 1) return exp ? go_local<1, true>(P, s) : go_local<1, false>(P, s);
     if (P.R == 2) return exp ? go_local<2, true>(P, s) : go_local<2, false>(P, s);
@@ -985,6 +1176,24 @@ hipError_t go_local_batched(const BatchLaunch &B, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int R>
+hipError_t go_quarter_batched(const BatchLaunch &B, hipStream_t s) {
+    if (B.nitems <= 0) return hipSuccess;
+    if (B.safe)
+        hipLaunchKernelGGL((k_pair_quarter_batched<R, true>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_pair_quarter_batched<R, false>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+template <int R>
+int occ_quarter() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_quarter_batched<R, false>, 256, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
 template <int R, bool EXP>
 int occ_local() {
     int nb = 0;
@@ -1011,13 +1220,16 @@ int occ_prec(int R, int mode) {
 }  // namespace
 
 int pair_local_batched_occupancy(int R, int jsrc) {
+    if (jsrc == 4) return R == 2 ? occ_quarter<2>() : occ_quarter<1>();
     if (R == 2) return jsrc == 3 ? occ_local<2, true>() : occ_local<2, false>();
     return jsrc == 3 ? occ_local<1, true>() : occ_local<1, false>();
 }
 
 hipError_t launch_pair_local_batched(const BatchLaunch &B, int jsrc, hipStream_t s) {
     if (B.block != 256 || B.mode != MODE_ACC || B.prec != P_MIXED || !B.lay || !B.lo.perm) return hipErrorInvalidValue;
-    if (jsrc != 2 && jsrc != 3) return hipErrorInvalidValue;
+    if (jsrc != 2 && jsrc != 3 && jsrc != 4) return hipErrorInvalidValue;
+    if (jsrc == 4)
+        return B.R == 1 ? go_quarter_batched<1>(B, s) : (B.R == 2 ? go_quarter_batched<2>(B, s) : hipErrorInvalidValue);
     if (B.R == 1) return jsrc == 3 ? go_local_batched<1, true>(B, s) : go_local_batched<1, false>(B, s);
     if (B.R == 2) return jsrc == 3 ? go_local_batched<2, true>(B, s) : go_local_batched<2, false>(B, s);
     return hipErrorInvalidValue;
@@ -1041,14 +1253,14 @@ int pair_batched_occupancy(int prec, int R, int block, int mode) {
 }
 
 bool pair_config_supported(int prec, int R, int block, int jsrc, int mode) {
-    if (jsrc == 2 || jsrc == 3) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
+    if (jsrc >= 2 && jsrc <= 4) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
     if (prec < 0 || prec > 2 || (jsrc != 0 && jsrc != 1)) return false;
     if (mode != MODE_ACC) return block == 256 && (R == 1 || R == 2);
     return (block == 128 || block == 256) && (R == 1 || R == 2 || R == 4);
 }
 
 hipError_t launch_pair(const PairLaunch &P, hipStream_t s) {
-    if (P.jsrc == 2 || P.jsrc == 3) return pick_local(P, s);
+    if (P.jsrc >= 2 && P.jsrc <= 4) return pick_local(P, s);
     switch (P.sc.prec) {
         case P_FP64: return pick_mode<P_FP64>(P, s);
         case P_MIXED: return pick_mode<P_MIXED>(P, s);

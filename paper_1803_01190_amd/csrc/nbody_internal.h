@@ -38,13 +38,15 @@ struct State {
     double *vx, *vy, *vz;
 };
 
-// Spatial order of one system (jsrc = 2 plans): particles sorted along a
-// Morton curve, their positions and masses in that order, and a bounding box
-// (min x, y, z, max x, y, z) per tile of 256 sorted particles.
+// Spatial order of one system (jsrc = 2, 3 and 4 plans): particles sorted
+// along a Morton curve, their positions and masses in that order, and a
+// bounding box (min x, y, z, max x, y, z) per tile of 256 sorted particles and
+// per quarter tile of 64 (quarter q of tile t at qbox[24 t + 6 q]).
 struct LocalOrder {
     const int32_t *perm;                   // sorted position -> particle index
     const double *px, *py, *pz, *pm;
     const double *tbox;
+    const double *qbox;
 };
 
 // One single-system pair-sum launch: targets [i0, i1), sources [0, n).

@@ -1,7 +1,8 @@
 // Spatial order of one system for the local mixed pair sums (plans with
-// jsrc = 2 and 3): particles sorted along a Morton (Z-order) curve of their
+// jsrc = 2, 3 and 4): particles sorted along a Morton (Z-order) curve of their
 // positions, so that each tile of 256 consecutive sorted particles is
-// spatially compact, and a bounding box per tile.  The pair kernels then form
+// spatially compact, a bounding box per tile, and one per quarter tile (64
+// sorted particles, one wave's share of a tile).  The pair kernels then form
 // float32 separations from tile-local float32 coordinates for tiles that are
 // far from a workgroup's targets (accel.hip k_pair_local, jerk.hip).
 //
@@ -40,8 +41,11 @@ __device__ __forceinline__ double wmax(double v) {
 
 // Min and max of x, y, z over [b, e) with stride, reduced over the
 // workgroup; lane 0 writes out[0..5] = (min x, min y, min z, max x, max y, max z).
+// With quarters != NULL (one tile: e - b <= stride = 256, so wave w holds
+// [b + 64 w, b + 64 w + 64)), lane 0 of each wave also writes its own box to
+// quarters[6 w .. 6 w + 5]; an empty quarter gets (DBL_MAX, -DBL_MAX).
 __device__ void block_box(const double *x, const double *y, const double *z, int64_t b, int64_t e,
-                          int64_t stride, double *out) {
+                          int64_t stride, double *out, double *quarters = nullptr) {
     double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     for (int64_t i = b + threadIdx.x; i < e; i += stride) {
         const double p[3] = {x[i], y[i], z[i]};
@@ -54,6 +58,7 @@ __device__ void block_box(const double *x, const double *y, const double *z, int
     for (int c = 0; c < 3; ++c) {
         const double a = wmin(lo[c]), bb = wmax(hi[c]);
         if (l == 0) { part[w][c] = a; part[w][3 + c] = bb; }
+        if (quarters && l == 0) { quarters[6 * w + c] = a; quarters[6 * w + 3 + c] = bb; }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -298,22 +303,24 @@ __global__ __launch_bounds__(kT) void k_gather(State st, int64_t n, const int32_
     }
 }
 
-// One workgroup per tile of 256 sorted particles.
+// One workgroup per tile of 256 sorted particles: its box and its four
+// quarter boxes.
 __global__ __launch_bounds__(kT) void k_tile_box(const double *px, const double *py, const double *pz, int64_t n,
-                                                 double *tbox) {
+                                                 double *tbox, double *qbox) {
     const int64_t b = (int64_t)blockIdx.x * kT;
-    block_box(px, py, pz, b, std::min<int64_t>(n, b + kT), kT, tbox + 6 * (int64_t)blockIdx.x);
+    block_box(px, py, pz, b, std::min<int64_t>(n, b + kT), kT, tbox + 6 * (int64_t)blockIdx.x,
+              qbox + 24 * (int64_t)blockIdx.x);
 }
 
 // Batches: tile g is tile k = g - tbase[b] of system b (tiles of 256 sorted
 // particles counted from the system's first).
 __global__ __launch_bounds__(kT) void k_tile_box_batched(const double *px, const double *py, const double *pz,
                                                          const int64_t *off, const int64_t *tbase, int32_t B,
-                                                         double *tbox) {
+                                                         double *tbox, double *qbox) {
     const int64_t g = blockIdx.x;
     const int32_t b = segment_of(tbase, B, g);
     const int64_t lo = off[b] + (g - tbase[b]) * kT;
-    block_box(px, py, pz, lo, std::min<int64_t>(off[b + 1], lo + kT), kT, tbox + 6 * g);
+    block_box(px, py, pz, lo, std::min<int64_t>(off[b + 1], lo + kT), kT, tbox + 6 * g, qbox + 24 * g);
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -338,7 +345,7 @@ SortShape sort_shape(int64_t n) {
 // `tiles` tiles and nsys systems (box: one per system).  The sort ping-pongs
 // between (key_a, idx_a) and (key_b, idx_b).
 struct Layout {
-    size_t key_a, key_b, idx_a, idx_b, px, py, pz, pm, tbox, parts, box, hist, tot, total;
+    size_t key_a, key_b, idx_a, idx_b, px, py, pz, pm, tbox, qbox, parts, box, hist, tot, total;
 };
 
 Layout layout(int64_t n, int64_t tiles_in, int32_t nsys) {
@@ -356,6 +363,7 @@ Layout layout(int64_t n, int64_t tiles_in, int32_t nsys) {
     L.pz = take(8 * nn);
     L.pm = take(8 * nn);
     L.tbox = take(48 * tiles);
+    L.qbox = take(192 * tiles);
     L.parts = take(48 * kParts);
     L.box = take(48 * (size_t)std::max(nsys, 1));
     L.hist = take(4 * (size_t)kBins * sort_shape(n).nb);
@@ -413,7 +421,7 @@ hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOr
     uint64_t *key_a = (uint64_t *)(base + L.key_a), *key_b = (uint64_t *)(base + L.key_b);
     int32_t *idx_a = (int32_t *)(base + L.idx_a), *idx_b = (int32_t *)(base + L.idx_b);
     double *px = (double *)(base + L.px), *py = (double *)(base + L.py), *pz = (double *)(base + L.pz);
-    double *pm = (double *)(base + L.pm), *tbox = (double *)(base + L.tbox);
+    double *pm = (double *)(base + L.pm), *tbox = (double *)(base + L.tbox), *qbox = (double *)(base + L.qbox);
     double *parts = (double *)(base + L.parts), *box = (double *)(base + L.box);
     uint32_t *hist = (uint32_t *)(base + L.hist), *tot = (uint32_t *)(base + L.tot);
     hipLaunchKernelGGL(k_box_partial, dim3(kParts), dim3(kT), 0, s, st, n, parts);
@@ -425,12 +433,13 @@ hipError_t launch_local_order(const State &st, int64_t n, void *scratch, LocalOr
     const int32_t *perm = idx_a;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kT), 0, s, st, n, perm, px, py, pz, pm);
     const int64_t tiles = (n + kT - 1) / kT;
-    hipLaunchKernelGGL(k_tile_box, dim3((unsigned)tiles), dim3(kT), 0, s, px, py, pz, n, tbox);
+    hipLaunchKernelGGL(k_tile_box, dim3((unsigned)tiles), dim3(kT), 0, s, px, py, pz, n, tbox, qbox);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     out->perm = perm;
     out->px = px; out->py = py; out->pz = pz; out->pm = pm;
     out->tbox = tbox;
+    out->qbox = qbox;
     return hipSuccess;
 }
 
@@ -445,6 +454,7 @@ hipError_t launch_batch_order(const State &st, const int64_t *off, const int64_t
     int32_t *idx_a = (int32_t *)(base + L.idx_a), *idx_b = (int32_t *)(base + L.idx_b);
     double *px = (double *)(base + L.px), *py = (double *)(base + L.py), *pz = (double *)(base + L.pz);
     double *pm = (double *)(base + L.pm), *tbox = (double *)(base + L.tbox), *boxes = (double *)(base + L.box);
+    double *qbox = (double *)(base + L.qbox);
     uint32_t *hist = (uint32_t *)(base + L.hist), *tot = (uint32_t *)(base + L.tot);
     hipLaunchKernelGGL(k_sys_box, dim3((unsigned)B), dim3(kT), 0, s, st, off, boxes);
     hipLaunchKernelGGL(k_morton_batched, dim3(grid_for(ntot)), dim3(kT), 0, s, st, off, B, ntot, boxes, key_a);
@@ -453,12 +463,14 @@ hipError_t launch_batch_order(const State &st, const int64_t *off, const int64_t
     if (e != hipSuccess) return e;
     const int32_t *perm = in_b ? idx_b : idx_a;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kT), 0, s, st, ntot, perm, px, py, pz, pm);
-    hipLaunchKernelGGL(k_tile_box_batched, dim3((unsigned)ntiles), dim3(kT), 0, s, px, py, pz, off, tbase, B, tbox);
+    hipLaunchKernelGGL(k_tile_box_batched, dim3((unsigned)ntiles), dim3(kT), 0, s, px, py, pz, off, tbase, B, tbox,
+                       qbox);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     out->perm = perm;
     out->px = px; out->py = py; out->pz = pz; out->pm = pm;
     out->tbox = tbox;
+    out->qbox = qbox;
     return hipSuccess;
 }
 

@@ -17,7 +17,11 @@ systems and zero softening (measured worst case: about 12u for either form).
 It also shows the criterion is needed: for targets next to the tile both
 forms lose the bound.  The jerk's far-tile form (velocities relative to the
 velocity of the tile's first source) is checked the same way on the
-kinematics of a rotating disk (measured worst case about 13u)."""
+kinematics of a rotating disk (measured worst case about 13u).  The
+quarter-tile form (far test per wave and per quarter of 64 sources, far
+quarters relative to the quarter's centre, near ones float64-formed, one
+float32 sum over the tile) is checked on elongated tiles whose quarters fall
+on both sides of the criterion."""
 import numpy as np
 import pytest
 
@@ -206,3 +210,58 @@ def test_far_tile_jerk_on_disk_kinematics(gap_over_diag):
         worst = max(worst, float((np.linalg.norm(got - f, axis=1) / scale).max()))
     assert worst <= 2e-5, worst
     assert worst <= 100 * U, worst
+
+
+def quarter_tile(xs, m, xt, eps2):
+    """The quarter-tile form (jsrc 4) for one wave: the far test per quarter
+    of 64 sources against the box of the wave's targets, far quarters
+    subtracting float32 coordinates relative to the quarter's centre, near
+    quarters rounding float64 differences; all terms into one float32 sum.
+    Returns the sum and the number of far quarters."""
+    tlo, thi = xt.min(0), xt.max(0)
+    e2 = np.float32(eps2)
+    acc = np.zeros((xt.shape[0], 3), np.float32)
+    nfar = 0
+    for q in range(T // 64):
+        s = slice(64 * q, 64 * q + 64)
+        lo, hi = xs[s].min(0), xs[s].max(0)
+        g = np.maximum(0.0, np.maximum(lo - thi, tlo - hi))
+        far = (g * g).sum() > ((hi - lo) ** 2).sum()
+        nfar += int(far)
+        if far:
+            c = 0.5 * (lo + hi)
+            sj, ti = f32(xs[s] - c), f32(xt - c)
+        for j in range(64 * q, 64 * q + 64):
+            d = (sj[j - 64 * q][None, :] - ti) if far else f32(xs[j][None, :] - xt)
+            r2 = fma32(d[:, 0], d[:, 0], fma32(d[:, 1], d[:, 1], fma32(d[:, 2], d[:, 2], np.full(len(d), e2))))
+            y = np.where(r2 > 0, rsq32(np.where(r2 > 0, r2, 1)), np.float32(0))
+            sc = (np.float32(m[j]) * y) * (y * y)
+            for k in range(3):
+                acc[:, k] = fma32(sc, d[:, k], acc[:, k])
+    return acc.astype(np.float64), nfar
+
+
+@pytest.mark.parametrize("shift", [0.0, 1.0e3])
+def test_quarter_tile_form_within_mixed_bound(shift):
+    # an elongated tile whose quarters follow one another along x (as along a
+    # space-filling curve) and a wave's 64 targets in a clump near one end:
+    # quarters far from the clump take the quarter-local form, the others
+    # float64-formed separations; the tile's float32 sum stays inside the
+    # mixed bound, and both kinds of quarter occur
+    rng = np.random.default_rng(7 + int(shift))
+    worst, nfars = 0.0, []
+    for trial in range(6):
+        length = rng.uniform(4.0, 8.0)
+        xs = rng.uniform(0.0, 1.0, (T, 3)) * np.array([length, 1.0, rng.uniform(0.05, 1.0)])
+        xs = xs[np.argsort(xs[:, 0], kind="stable")] + shift
+        m = rng.uniform(0.5, 1.5, T) / T
+        xt = xs[rng.integers(0, 16)] + rng.normal(size=(64, 3)) * 0.05
+        for eps2 in (0.0, 1e-4):
+            got, nfar = quarter_tile(xs, m, xt, eps2)
+            f, scale = exact(xs, m, xt, eps2)
+            err = np.linalg.norm(got - f, axis=1) / scale
+            worst = max(worst, float(err.max()))
+            nfars.append(nfar)
+    assert worst <= (10 + 255) * U, worst
+    assert worst <= 40 * U, worst
+    assert 0 < min(nfars) and max(nfars) < 4, nfars

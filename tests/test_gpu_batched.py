@@ -69,7 +69,8 @@ BATCH_PLANS = [None,  # the default plan
                {"R": 1, "block": 256, "split": 0, "jsrc": 0},
                {"R": 2, "block": 256, "split": 2, "jsrc": 0},
                {"R": 1, "block": 256, "split": 3, "jsrc": 3},
-               {"R": 2, "block": 256, "split": 1, "jsrc": 2}]
+               {"R": 2, "block": 256, "split": 1, "jsrc": 2},
+               {"R": 2, "block": 256, "split": 3, "jsrc": 4}]
 
 
 def plan_id(p):
@@ -204,15 +205,19 @@ LARGE_SPECS = [
     ("disk", 5000, 24, 0.02, "fp64", True, 1e-3),
     ("plummer", 0, 25, 0.01, "mixed", False, 1e-3),
     ("disk", 32768, 26, 0.02, "mixed", True, 1e-3),
+    ("plummer", 9000, 27, 0.01, "mixed", False, 1e-3),
 ]
 
 
 @pytest.mark.parametrize("bplan", [{"R": 1, "block": 256, "split": 16, "jsrc": 3},
                                    {"R": 2, "block": 256, "split": 0, "jsrc": 2},
-                                   {"R": 1, "block": 256, "split": 7, "jsrc": 2}], ids=plan_id)
+                                   {"R": 1, "block": 256, "split": 7, "jsrc": 2},
+                                   {"R": 2, "block": 256, "split": 16, "jsrc": 4},
+                                   {"R": 1, "block": 256, "split": 0, "jsrc": 4}], ids=plan_id)
 def test_spatial_order_batch_large_systems(nb, ctx, orc, bplan):
-    # mixed systems of 2^15 particles or more are summed in their own spatial
-    # order inside the batch (the smaller ones with LDS tiles): bitwise the
+    # mixed systems of 2^15 particles or more (2^12 under the quarter-tile
+    # form) are summed in their own spatial order inside the batch (the
+    # smaller ones with LDS tiles): bitwise the
     # single-system sums under the reported plans, and the oracle's on
     # sampled rows; one graph-replayed KDK step equals the eager one
     print(f"[case] batched large systems plan {bplan}", flush=True)
@@ -230,7 +235,8 @@ def test_spatial_order_batch_large_systems(nb, ctx, orc, bplan):
         for k, (sp, ic, prm) in enumerate(zip(LARGE_SPECS, parts, prms)):
             lo, hi = off[k], off[k + 1]
             plan = nb.nbody_batch_system_plan(ctx, b, k)
-            if sp[4] == "mixed" and sp[1] >= 1 << 15:
+            # spatial order from 2^15 particles on (2^12 for the quarter-tile form)
+            if sp[4] == "mixed" and sp[1] >= (1 << 12 if bplan["jsrc"] == 4 else 1 << 15):
                 assert plan["jsrc"] == bplan["jsrc"], (k, plan)
             elif sp[1] > 0:
                 assert plan["jsrc"] == 0, (k, plan)

@@ -70,6 +70,33 @@ def test_disk_2p20_sampled(nb, ctx, orc, disk20, prec):
         assert net <= 1e-13 * scale, (net, scale)
 
 
+# the quarter-tile form (jsrc 4) at the sizes and splits of the tuned mixed
+# plans, on the same sampled rows and gate
+@pytest.mark.parametrize("log2n,plan", [(20, {"R": 1, "block": 256, "split": 32, "jsrc": 4}),
+                                        (17, {"R": 2, "block": 256, "split": 16, "jsrc": 4})],
+                         ids=["2p20R1s32", "2p17R2s16"])
+def test_disk_quarter_plan_sampled(nb, ctx, orc, disk20, log2n, plan):
+    n = 1 << log2n
+    print(f"[case] disk 2^{log2n} mixed quarter-tile plan {plan} sampled rows", flush=True)
+    ic = disk20 if log2n == 20 else wl.exp_disk(n, 2)
+    h = wl.default_halo()
+    prm = nb.Params(eps=0.02, prec=nb.NB_MIXED, halo=True, halo_v2=h.v2, halo_rc=h.rc)
+    s = nb.System.from_arrays(ic)
+    nb.nbody_plan_set(ctx, nb.NB_MIXED, n, plan)
+    try:
+        nb.nbody_accel(ctx, s, prm)
+    finally:
+        nb.nbody_plan_set(ctx, nb.NB_MIXED, n, None)
+    rng = np.random.default_rng(13)
+    rows = np.sort(rng.choice(n, size=512, replace=False))
+    rt = torch.as_tensor(rows, device="cuda")
+    got = torch.stack([s["ax"][rt], s["ay"][rt], s["az"][rt]]).cpu().numpy()
+    ref, A = oracle_rows(orc, ic, rows, 0.02, h)
+    e = force_errors(got, ref, A)
+    print(f"[err] 2^{log2n} quarter plan: {e}", flush=True)
+    assert e["eps_rms"] <= GATE["mixed"] and e["eps_cond"] <= GATE["mixed"], e
+
+
 # acceleration and jerk of the fourth-order Hermite scheme in the launch
 # configuration the Hermite benchmark times (the tuned jerk plans: for mixed,
 # the spatially ordered plan with R 1 and a 32-way split from N = 2^17 on)
