@@ -58,9 +58,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(prec: str):
+def load_traffic(prec: str, plan: dict = None):
     """HBM bytes per pair-sum launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel source or the launch plan changed since
+    it was taken (the split partial sums are part of the traffic)."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         with open(path) as f:
@@ -68,6 +69,8 @@ def load_traffic(prec: str):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
+        return None
+    if plan is not None and rec.get("plans", {}).get(prec) != plan:
         return None
     return rec.get("per_launch_bytes", {}).get(prec)
 
@@ -293,7 +296,7 @@ def main():
             json.dump({"gfx950": {k: {str(log2n): v["plan"]} for k, v in results.items()}}, f, indent=1)
     head = precs[0]
     r0 = results[head]
-    traffic = load_traffic(head)
+    traffic = load_traffic(head, r0["plan"])
     out = {
         "metric": METRIC,
         "value": r0["value"],
