@@ -418,7 +418,9 @@ NBODY_API nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, c
  * whole systems (all n sources; one warm-up and two timed launches) until
  * budget_ms is spent (<= 0: every candidate; at least one is always timed;
  * each is timed over 2 to 16 launches, at least 20 ms when launches allow);
- * the fastest is pinned for the key of (prec, n) and returned.  Candidates:
+ * the fastest is pinned for the key of (prec, n) and returned, except that
+ * plans within 1% of the fastest count as ties, won by the one with the
+ * fewest split partial sums (the smallest split; scratch and HBM traffic).  Candidates:
  * the key's current plan first, then for NB_MIXED the spatially ordered
  * plans (jsrc 3, 2 and 4: accelerations; jsrc 2: jerk), then every R, block
  * (the j-tile length) and power-of-two split up to 64 (chunks of at least
@@ -437,7 +439,8 @@ NBODY_API nbody_status nbody_autotune_sys(nbody_ctx *ctx, int32_t prec, const nb
                                           const nbody_params *prm, double budget_ms, nbody_plan *out);
 /* Time batch plans (R 1 and 2; jsrc 4, 3, 2 and 0 when the batch has NB_MIXED
  * systems; chunks of 0, 8, 16, 32 and 64 source tiles) with
- * nbody_accel_batched on the caller's state, set the fastest on the batch,
+ * nbody_accel_batched on the caller's state, set the fastest on the batch
+ * (ties within 1% go to the plan with the fewest chunk partial sums),
  * pin it (class NB_PLAN_BATCH, keyed by the largest system) and leave the
  * accelerations as it gives them.  Synchronous; rebuilds the batch's tables. */
 NBODY_API nbody_status nbody_batch_autotune(nbody_ctx *ctx, nbody_batch *batch, const nbody_sys *all,

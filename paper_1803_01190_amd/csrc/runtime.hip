@@ -1449,17 +1449,24 @@ static std::vector<nbody_plan> tune_candidates(nbody_ctx *ctx, int prec, int cls
     return cand;
 }
 
+// Plans within this fraction of the fastest time count as ties, decided by
+// their split partial sums (scratch and HBM traffic).
+constexpr double kTuneTie = 0.01;
+
 // Time candidates (one warm-up and two timed launches each, on the NULL
-// stream) until budget_ms is spent (budget_ms <= 0: all); *best = fastest.
-template <class Launch>
+// stream) until budget_ms is spent (budget_ms <= 0: all).  *best = the
+// candidate with the fewest partial-sum bytes (cost(plan)) among those
+// within kTuneTie of the fastest, the earliest in the list among equals.
+template <class Launch, class Cost>
 static nbody_status time_candidates(nbody_ctx *ctx, const std::vector<nbody_plan> &cand, double budget_ms,
-                                    Launch launch, nbody_plan *best) {
+                                    Launch launch, Cost cost, nbody_plan *best) {
     hipEvent_t a = nullptr, bev = nullptr;
     HIPCHECK(ctx, hipEventCreate(&a));
     HIPCHECK(ctx, hipEventCreate(&bev));
     const bool prof = ctx->prof;
     ctx->prof = false;
     double spent = 0.0, best_ms = -1.0;
+    std::vector<double> per_ms;  // per launch, in candidate order
     nbody_status result = NB_OK;
     for (size_t c = 0; c < cand.size(); ++c) {
         if (c > 0 && budget_ms > 0 && spent >= budget_ms) break;
@@ -1484,7 +1491,17 @@ static nbody_status time_candidates(nbody_ctx *ctx, const std::vector<nbody_plan
         (void)hipEventElapsedTime(&ms, a, bev);
         spent += ms + ms1;
         const double per = ms / reps;
-        if (best_ms < 0 || per < best_ms) { best_ms = per; *best = cand[c]; }
+        per_ms.push_back(per);
+        if (best_ms < 0 || per < best_ms) best_ms = per;
+    }
+    if (result == NB_OK && !per_ms.empty()) {
+        size_t pick = 0;
+        bool have = false;
+        for (size_t c = 0; c < per_ms.size(); ++c) {
+            if (per_ms[c] > best_ms * (1.0 + kTuneTie)) continue;
+            if (!have || cost(cand[c]) < cost(cand[pick])) { pick = c; have = true; }
+        }
+        *best = cand[pick];
     }
     ctx->prof = prof;
     (void)hipEventDestroy(a);
@@ -1525,8 +1542,10 @@ static nbody_status autotune_on(nbody_ctx *ctx, int prec, int cls, const nbody_s
         return run_pair(ctx, st, sc, 0, n, MODE_ACC, pl, 0, 0.0, nullptr);
     };
     const std::vector<nbody_plan> cand = tune_candidates(ctx, prec, cls, n);
+    // split partial sums: 4 (6 for the jerk) doubles per target and chunk
+    auto cost = [](const nbody_plan &pl) -> double { return pl.split > 1 ? (double)pl.split : 0.0; };
     nbody_plan best = cand.front();
-    nbody_status r = time_candidates(ctx, cand, budget_ms, launch, &best);
+    nbody_status r = time_candidates(ctx, cand, budget_ms, launch, cost, &best);
     if (r == NB_OK) r = launch(best);  // the outputs as the pinned plan gives them
     (void)hipDeviceSynchronize();
     if (tmp) (void)hipFree(tmp);
@@ -1640,8 +1659,11 @@ nbody_status nbody_batch_autotune(nbody_ctx *ctx, nbody_batch *b, const nbody_sy
             }
             return batch_pair(ctx, b, st, 0.0, nullptr);
         };
+        // chunk partial sums: one set per chunk of `split` source tiles (0:
+        // whole systems, none), so fewer for longer chunks
+        auto cost = [](const nbody_plan &pl) -> double { return pl.split > 0 ? 1.0 / pl.split : 0.0; };
         nbody_plan best = cand.front();
-        r = time_candidates(ctx, cand, budget_ms, launch, &best);
+        r = time_candidates(ctx, cand, budget_ms, launch, cost, &best);
         if (r == NB_OK) r = launch(best);
         (void)hipDeviceSynchronize();
         if (r != NB_OK) return r;
