@@ -76,7 +76,7 @@ typedef enum {
  *             refined (first-order binomial step on y^3, leaving a one-signed
  *             error below 2.1e-14 per pair term, under the float64 sum's).
  *   NB_MIXED: pair separations formed in float64 from the float64 positions
- *             and then rounded to float32 (plans with jsrc 2, 3 or 4: for
+ *             and then rounded to float32 (plans with jsrc 2 to 5: for
  *             source tiles, or quarter tiles, far from the targets, from
  *             float32 coordinates relative to the tile's or quarter's centre,
  *             with a few u of relative error, u = 2^-24);
@@ -140,13 +140,15 @@ typedef struct {
  *         order (>= 1; small systems use it to fill the GPU; ignored, i.e. 1,
  *         for NB_FP32)
  *   jsrc  0 = j tiles staged through LDS, 1 = j read through the scalar
- *         cache straight into SGPR operands, 2, 3 and 4 = NB_MIXED
+ *         cache straight into SGPR operands, 2 to 5 = NB_MIXED
  *         accelerations in a spatial (Morton) order: far source tiles use
  *         float32 coordinates relative to the tile's centre, subtracted per
  *         pair (2) or through the expanded squared distance (3); or (4) the
  *         far test is taken per wave (its 64 R targets) and per quarter of the
  *         source tile (64 sources), and far quarters subtract coordinates
- *         relative to the quarter's centre (256 lanes, R = 1 or 2, whole
+ *         relative to the quarter's centre; or (5) tiles far from the
+ *         workgroup's targets take the expanded form of 3 and the others the
+ *         quarter test of 4 (256 lanes, R = 1 or 2, whole
  *         system only: nbody_accel_rows returns NB_ENOTSUP).  The ordering is
  *         the library's own kernels (nbody_spatial_order), so these plans can
  *         be captured into a HIP graph like the others. */
@@ -193,7 +195,7 @@ NBODY_API nbody_status nbody_accel(nbody_ctx *ctx, const nbody_sys *sys, const n
  * beside the spatial order; a split that had to shrink changes the summation
  * order, so the result then agrees with nbody_accel to rounding, not
  * bitwise.  Sizes beyond the maximum return NB_EINVAL with a message: a
- * spatially ordered plan (jsrc 2, 3 or 4) needs about 57 B per particle, so it
+ * spatially ordered plan (jsrc 2 to 5) needs about 57 B per particle, so it
  * is limited to n of about 2.3e6; jsrc 0 and 1 plans with split 1 need no
  * scratch at all.  Nothing in the array needs to start at zero (every call
  * overwrites what it reads).  All calls on one GPU share its array: calls
@@ -206,14 +208,14 @@ NBODY_API nbody_status nbody_accel_static(nbody_ctx *ctx, const nbody_sys *sys, 
  * are sources).  Rows [i0, i1) are bitwise equal to those of nbody_accel
  * under the same plan; the other rows are untouched.  This is one GPU's
  * share when the targets of one system are split across several GPUs.
- * A spatially ordered plan (jsrc 2, 3 or 4) takes its targets in its own
+ * A spatially ordered plan (jsrc 2 to 5) takes its targets in its own
  * order: a proper subrange of particle indices under such a plan returns
  * NB_ENOTSUP; nbody_accel_order_rows takes ranges of that order. */
 NBODY_API nbody_status nbody_accel_rows(nbody_ctx *ctx, const nbody_sys *sys, const nbody_params *prm,
                               int64_t i0, int64_t i1, void *stream);
 
 /* The i-split of the paper's Section 2 (each GPU sums its share of the
- * targets against all sources) for a spatially ordered plan (jsrc 2, 3 or 4),
+ * targets against all sources) for a spatially ordered plan (jsrc 2 to 5),
  * whose targets are taken in the system's Morton order: the accelerations of
  * the particles at sorted positions k in [k0, k1) (particles perm[k], see
  * nbody_spatial_order), bitwise equal to those of nbody_accel under the same
@@ -302,7 +304,7 @@ NBODY_API nbody_status nbody_surface_density(nbody_ctx *ctx, const nbody_sys *sy
                                              double x0, double y0, double sx, double sy,
                                              uint32_t *counts, void *stream);
 
-/* The spatial order behind the jsrc 2, 3 and 4 plans (the GPU-side design
+/* The spatial order behind the jsrc 2 to 5 plans (the GPU-side design
  * choice that lets far source tiles use tile-local float32 coordinates; the
  * paper's kernel keeps the particles' own order).  Writes perm[k] = index of
  * the particle at sorted position k, for the stable ascending sort of the
@@ -351,8 +353,8 @@ NBODY_API nbody_status nbody_batch_reset(nbody_ctx *ctx, nbody_batch *batch, int
  *          in ceil(n / (256 split)) chunks whose partial sums are reduced in
  *          a fixed order (0: whole systems, no chunks; float32 systems never
  *          split);
- *   jsrc   for the NB_MIXED systems: 0 (LDS source tiles) or 2, 3, 4
- *          (systems of at least 2^15 particles, 2^12 for jsrc 4, in spatial
+ *   jsrc   for the NB_MIXED systems: 0 (LDS source tiles) or 2 to 5
+ *          (systems of at least 2^15 particles, 2^12 for jsrc 4 and 5, in spatial
  *          order, far tiles or quarters in the tile-local float32 forms of
  *          the single-system plans with the same jsrc; smaller ones with LDS
  *          source tiles).
@@ -422,7 +424,7 @@ NBODY_API nbody_status nbody_plan_set(nbody_ctx *ctx, int32_t prec, int64_t n, c
  * plans within 1% of the fastest count as ties, won by the one with the
  * fewest split partial sums (the smallest split; scratch and HBM traffic).  Candidates:
  * the key's current plan first, then for NB_MIXED the spatially ordered
- * plans (jsrc 3, 2 and 4: accelerations; jsrc 2: jerk), then every R, block
+ * plans (jsrc 3, 5, 2 and 4: accelerations; jsrc 2: jerk), then every R, block
  * (the j-tile length) and power-of-two split up to 64 (chunks of at least
  * two source tiles) the kernels take.  Kernel loop
  * unrolling is fixed at build time (four sources per step of an LDS tile
@@ -437,7 +439,7 @@ NBODY_API nbody_status nbody_autotune(nbody_ctx *ctx, int32_t prec, int64_t n, d
                             nbody_plan *out);
 NBODY_API nbody_status nbody_autotune_sys(nbody_ctx *ctx, int32_t prec, const nbody_sys *sys,
                                           const nbody_params *prm, double budget_ms, nbody_plan *out);
-/* Time batch plans (R 1 and 2; jsrc 4, 3, 2 and 0 when the batch has NB_MIXED
+/* Time batch plans (R 1 and 2; jsrc 4, 5, 3, 2 and 0 when the batch has NB_MIXED
  * systems; chunks of 0, 8, 16, 32 and 64 source tiles) with
  * nbody_accel_batched on the caller's state, set the fastest on the batch
  * (ties within 1% go to the plan with the fewest chunk partial sums),

@@ -592,6 +592,44 @@ __device__ __forceinline__ State sorted_state(const LocalSys &O) {
     return sv;
 }
 
+// One far source tile [jt, min(jt + 256, je)) in the expanded form (jsrc = 3),
+// with coordinates relative to the tile's centre ctr.  Flushes the tile sums;
+// the caller's barrier after it protects the LDS tiles.
+template <int R, bool SAFE>
+__device__ __forceinline__ void expanded_tile(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t jt, int64_t je,
+                                              const double *ctr, double eps2, JL *ftile, float *fmass) {
+    constexpr int BLOCK = 256;
+    const int t = threadIdx.x;
+    const int64_t j = jt + t;
+    const bool ok = j < je;
+    JL e{0.0f, 0.0f, 0.0f, 0.0f};
+    const double mj = ok ? O.pm[j] : 0.0;
+    if (ok) {
+        const double dx = O.px[j] - ctr[0], dy = O.py[j] - ctr[1], dz = O.pz[j] - ctr[2];
+        e.x = (float)dx; e.y = (float)dy; e.z = (float)dz;
+        e.m = (float)(dx * dx + dy * dy + dz * dz);
+    }
+    ftile[t] = e;
+    fmass[t] = (float)mj;
+    float wx[R], wy[R], wz[R], qi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double dx = L.xi[r] - ctr[0], dy = L.yi[r] - ctr[1], dz = L.zi[r] - ctr[2];
+        wx[r] = (float)(-2.0 * dx); wy[r] = (float)(-2.0 * dy); wz[r] = (float)(-2.0 * dz);
+        qi[r] = (float)(dx * dx + dy * dy + dz * dz + eps2);
+    }
+    const double m0 = O.pm[jt];
+    const bool um = __syncthreads_and(mj == m0) != 0;
+    if (um) {
+#pragma unroll 4
+        for (int k = 0; k < BLOCK; ++k) interact_expanded<R, SAFE, true>(L, ftile[k], 0.0f, wx, wy, wz, qi);
+    } else {
+#pragma unroll 4
+        for (int k = 0; k < BLOCK; ++k) interact_expanded<R, SAFE, false>(L, ftile[k], fmass[k], wx, wy, wz, qi);
+    }
+    flush_expanded(L, um, m0, ctr);
+}
+
 // Sum the sorted sources [jb, je) of one system into the lanes holding the
 // R * 256 sorted targets from ib.  Far tiles (box farther from the targets'
 // box than its own diagonal) take the tile-local float32 forms, the others
@@ -631,33 +669,7 @@ __device__ __forceinline__ void local_sweep(Lane<P_MIXED, R> &L, const LocalSys 
         const int64_t j = jt + t;
         const bool ok = j < je;
         if (EXP && gap2 > diag2) {  // far tile, expanded form (a uniform branch)
-            JL e{0.0f, 0.0f, 0.0f, 0.0f};
-            const double mj = ok ? O.pm[j] : 0.0;
-            if (ok) {
-                const double dx = O.px[j] - ctr[0], dy = O.py[j] - ctr[1], dz = O.pz[j] - ctr[2];
-                e.x = (float)dx; e.y = (float)dy; e.z = (float)dz;
-                e.m = (float)(dx * dx + dy * dy + dz * dz);
-            }
-            ftile[t] = e;
-            fmass[t] = (float)mj;
-            float wx[R], wy[R], wz[R], qi[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double dx = L.xi[r] - ctr[0], dy = L.yi[r] - ctr[1], dz = L.zi[r] - ctr[2];
-                wx[r] = (float)(-2.0 * dx); wy[r] = (float)(-2.0 * dy); wz[r] = (float)(-2.0 * dz);
-                qi[r] = (float)(dx * dx + dy * dy + dz * dz + eps2);
-            }
-            const double m0 = O.pm[jt];
-            const bool um = __syncthreads_and(mj == m0) != 0;
-            if (um) {
-#pragma unroll 4
-                for (int k = 0; k < BLOCK; ++k) interact_expanded<R, SAFE, true>(L, ftile[k], 0.0f, wx, wy, wz, qi);
-            } else {
-#pragma unroll 4
-                for (int k = 0; k < BLOCK; ++k)
-                    interact_expanded<R, SAFE, false>(L, ftile[k], fmass[k], wx, wy, wz, qi);
-            }
-            flush_expanded(L, um, m0, ctr);
+            expanded_tile<R, SAFE>(L, O, jt, je, ctr, eps2, ftile, fmass);
         } else if (!EXP && gap2 > diag2) {  // far tile (a uniform branch)
             JL e;
             e.x = ok ? (float)(O.px[j] - ctr[0]) : 0.0f;
@@ -794,15 +806,14 @@ __global__ __launch_bounds__(256) void k_pair_local_batched(BatchLaunch B) {
 // their distances (systems of a few thousand particles, three-dimensional
 // ones).  An equal-mass tile (block vote on the float64 masses) leaves the
 // mass out of both pair terms and applies the float64 mass at the flush.
-template <int R, bool SAFE>
-__device__ __forceinline__ void quarter_sweep(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t ib, int64_t jb,
-                                              int64_t je, double eps2, float eps2f, JL *ftile, JM *dtile) {
-    constexpr int BLOCK = 256;
-    const int t = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index (uniform)
+// Box of this wave's targets: the quarters ib / 64 + 4 r + w of its R groups
+// of 64 sorted targets (w: the wave; quarters past the system are left out).
+template <int R>
+__device__ __forceinline__ void wave_box(const LocalSys &O, int64_t ib, double *bmin, double *bmax) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (uniform)
     const int64_t nq = (O.n + 63) / 64;
-    // box of this wave's targets: quarters ib / 64 + 4 r + w
-    double bmin[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, bmax[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { bmin[c] = DBL_MAX; bmax[c] = -DBL_MAX; }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t q = ib / 64 + 4 * r + w;
@@ -814,77 +825,96 @@ __device__ __forceinline__ void quarter_sweep(Lane<P_MIXED, R> &L, const LocalSy
             }
         }
     }
-    for (int64_t jt = jb; jt < je; jt += BLOCK) {
-        const int64_t q0 = jt / 64;  // first quarter of the tile
-        // lane l tests quarter l % 4 (empty quarters, boxes (DBL_MAX, -DBL_MAX),
-        // test near); bit q of farq: quarter q is far from this wave's targets
-        bool far = false;
-        {
-            const double *qb = O.qbox + 6 * (q0 + (t & 3));
-            double gap2 = 0.0, diag2 = 0.0;
+}
+
+// One source tile [jt, min(jt + 256, je)) in the quarter-tile form, against the
+// lanes of a wave whose targets have the box (bmin, bmax).  Flushes the tile
+// sums; the caller's barrier after it protects the LDS tiles.
+template <int R, bool SAFE>
+__device__ __forceinline__ void quarter_tile(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t jt, int64_t je,
+                                             const double *bmin, const double *bmax, double eps2, float eps2f,
+                                             JL *ftile, JM *dtile) {
+    const int t = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index (uniform)
+    const int64_t q0 = jt / 64;  // first quarter of the tile
+    // lane l tests quarter l % 4 (empty quarters, boxes (DBL_MAX, -DBL_MAX),
+    // test near); bit q of farq: quarter q is far from this wave's targets
+    bool far = false;
+    {
+        const double *qb = O.qbox + 6 * (q0 + (t & 3));
+        double gap2 = 0.0, diag2 = 0.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double lo = qb[c], hi = qb[3 + c];
-                const double g = fmax(0.0, fmax(lo - bmax[c], bmin[c] - hi));
-                gap2 += g * g;
-                diag2 += (hi - lo) * (hi - lo);
-            }
-            far = gap2 > diag2;
+        for (int c = 0; c < 3; ++c) {
+            const double lo = qb[c], hi = qb[3 + c];
+            const double g = fmax(0.0, fmax(lo - bmax[c], bmin[c] - hi));
+            gap2 += g * g;
+            diag2 += (hi - lo) * (hi - lo);
         }
-        const uint32_t farq = (uint32_t)(__ballot(far) & 0xFull);
-        // stage source j in both forms: float64 (near quarters) and relative
-        // to the centre of its quarter (w) in float32 (far quarters)
-        const int64_t j = jt + t;
-        const bool ok = j < je;
-        const double xj = ok ? O.px[j] : 0.0, yj = ok ? O.py[j] : 0.0, zj = ok ? O.pz[j] : 0.0;
-        const double mj = ok ? O.pm[j] : 0.0;
-        {
-            const double *cq = O.qbox + 6 * (q0 + w);
-            JL e;
-            e.x = ok ? (float)(xj - 0.5 * (cq[0] + cq[3])) : 0.0f;
-            e.y = ok ? (float)(yj - 0.5 * (cq[1] + cq[4])) : 0.0f;
-            e.z = ok ? (float)(zj - 0.5 * (cq[2] + cq[5])) : 0.0f;
-            e.m = (float)mj;
-            ftile[t] = e;
-            JM d;
-            d.x = xj; d.y = yj; d.z = zj; d.m = (float)mj; d.pad = 0.0f;
-            dtile[t] = d;
-        }
-        const double m0 = O.pm[jt];
-        const bool um = __syncthreads_and(mj == m0) != 0;  // also the barrier after the stores
+        far = gap2 > diag2;
+    }
+    const uint32_t farq = (uint32_t)(__ballot(far) & 0xFull);
+    // stage source j in both forms: float64 (near quarters) and relative to
+    // the centre of its quarter (w) in float32 (far quarters)
+    const int64_t j = jt + t;
+    const bool ok = j < je;
+    const double xj = ok ? O.px[j] : 0.0, yj = ok ? O.py[j] : 0.0, zj = ok ? O.pz[j] : 0.0;
+    const double mj = ok ? O.pm[j] : 0.0;
+    {
+        const double *cq = O.qbox + 6 * (q0 + w);
+        JL e;
+        e.x = ok ? (float)(xj - 0.5 * (cq[0] + cq[3])) : 0.0f;
+        e.y = ok ? (float)(yj - 0.5 * (cq[1] + cq[4])) : 0.0f;
+        e.z = ok ? (float)(zj - 0.5 * (cq[2] + cq[5])) : 0.0f;
+        e.m = (float)mj;
+        ftile[t] = e;
+        JM d;
+        d.x = xj; d.y = yj; d.z = zj; d.m = (float)mj; d.pad = 0.0f;
+        dtile[t] = d;
+    }
+    const double m0 = O.pm[jt];
+    const bool um = __syncthreads_and(mj == m0) != 0;  // also the barrier after the stores
 #pragma unroll 1
-        for (int qd = 0; qd < 4; ++qd) {
-            const JL *fq = ftile + 64 * qd;
-            const JM *dq = dtile + 64 * qd;
-            if ((farq >> qd) & 1u) {
-                const double *cq = O.qbox + 6 * (q0 + qd);
-                const double cx = 0.5 * (cq[0] + cq[3]), cy = 0.5 * (cq[1] + cq[4]), cz = 0.5 * (cq[2] + cq[5]);
-                float rx[R], ry[R], rz[R];
+    for (int qd = 0; qd < 4; ++qd) {
+        const JL *fq = ftile + 64 * qd;
+        const JM *dq = dtile + 64 * qd;
+        if ((farq >> qd) & 1u) {
+            const double *cq = O.qbox + 6 * (q0 + qd);
+            const double cx = 0.5 * (cq[0] + cq[3]), cy = 0.5 * (cq[1] + cq[4]), cz = 0.5 * (cq[2] + cq[5]);
+            float rx[R], ry[R], rz[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    rx[r] = (float)(L.xi[r] - cx);
-                    ry[r] = (float)(L.yi[r] - cy);
-                    rz[r] = (float)(L.zi[r] - cz);
-                }
-                if (um) {
+            for (int r = 0; r < R; ++r) {
+                rx[r] = (float)(L.xi[r] - cx);
+                ry[r] = (float)(L.yi[r] - cy);
+                rz[r] = (float)(L.zi[r] - cz);
+            }
+            if (um) {
 #pragma unroll 4
-                    for (int k = 0; k < 64; ++k) interact_local<R, SAFE, true>(L, fq[k], rx, ry, rz, eps2f);
-                } else {
-#pragma unroll 4
-                    for (int k = 0; k < 64; ++k) interact_local<R, SAFE, false>(L, fq[k], rx, ry, rz, eps2f);
-                }
-            } else if (um) {
-#pragma unroll 4
-                for (int k = 0; k < 64; ++k) {
-                    const JM &f = dq[k];
-                    interact<P_MIXED, R, MODE_ACC, SAFE, true>(L, f.x, f.y, f.z, 0, 0, 0, 0, 0, eps2, eps2f);
-                }
+                for (int k = 0; k < 64; ++k) interact_local<R, SAFE, true>(L, fq[k], rx, ry, rz, eps2f);
             } else {
 #pragma unroll 4
-                for (int k = 0; k < 64; ++k) interact_src<P_MIXED, R, MODE_ACC, SAFE>(L, dq[k], eps2, eps2f);
+                for (int k = 0; k < 64; ++k) interact_local<R, SAFE, false>(L, fq[k], rx, ry, rz, eps2f);
             }
+        } else if (um) {
+#pragma unroll 4
+            for (int k = 0; k < 64; ++k) {
+                const JM &f = dq[k];
+                interact<P_MIXED, R, MODE_ACC, SAFE, true>(L, f.x, f.y, f.z, 0, 0, 0, 0, 0, eps2, eps2f);
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < 64; ++k) interact_src<P_MIXED, R, MODE_ACC, SAFE>(L, dq[k], eps2, eps2f);
         }
-        flush(L, um, m0);
+    }
+    flush(L, um, m0);
+}
+
+template <int R, bool SAFE>
+__device__ __forceinline__ void quarter_sweep(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t ib, int64_t jb,
+                                              int64_t je, double eps2, float eps2f, JL *ftile, JM *dtile) {
+    double bmin[3], bmax[3];
+    wave_box<R>(O, ib, bmin, bmax);
+    for (int64_t jt = jb; jt < je; jt += 256) {
+        quarter_tile<R, SAFE>(L, O, jt, je, bmin, bmax, eps2, eps2f, ftile, dtile);
         __syncthreads();
     }
 }
@@ -912,11 +942,73 @@ __device__ __forceinline__ void local_rows(const Lane<P_MIXED, R> &L, int64_t ib
     }
 }
 
-// Single system, jsrc = 4: the launch shape of k_pair_local.
+// Box of a workgroup's targets: the boxes of its R tiles of 256 sorted targets
+// from ib (tiles past the system are left out).
+template <int R>
+__device__ __forceinline__ void group_box(const LocalSys &O, int64_t ib, double *bmin, double *bmax) {
+    const int64_t ntile = (O.n + 255) / 256;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { bmin[c] = DBL_MAX; bmax[c] = -DBL_MAX; }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t tt = ib / 256 + r;
+        if (tt < ntile) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bmin[c] = fmin(bmin[c], O.tbox[6 * tt + c]);
+                bmax[c] = fmax(bmax[c], O.tbox[6 * tt + 3 + c]);
+            }
+        }
+    }
+}
+
+// Hybrid form (jsrc = 5): each tile first takes the workgroup-level far test of
+// the expanded form (jsrc 3); a tile near the workgroup's targets is then taken
+// in the quarter-tile form, so that its quarters far from a wave's own targets
+// still use float32 coordinates.  Where most tiles are far (large thin disks)
+// this keeps the expanded form's cheap pair term and moves part of the near
+// tiles' pairs to it.
 template <int R, bool SAFE>
-__global__ __launch_bounds__(256) void k_pair_quarter(PairLaunch P, int64_t chunk) {
-    __shared__ JL ftile[256];
-    __shared__ JM dtile[256];
+__device__ __forceinline__ void hybrid_sweep(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t ib, int64_t jb,
+                                             int64_t je, double eps2, float eps2f, JL *ftile, JM *dtile,
+                                             float *fmass) {
+    double gmin[3], gmax[3], wmin[3], wmax[3];
+    group_box<R>(O, ib, gmin, gmax);
+    wave_box<R>(O, ib, wmin, wmax);
+    for (int64_t jt = jb; jt < je; jt += 256) {
+        const double *tb = O.tbox + 6 * (jt / 256);
+        double gap2 = 0.0, diag2 = 0.0, ctr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double lo = tb[c], hi = tb[3 + c];
+            const double g = fmax(0.0, fmax(lo - gmax[c], gmin[c] - hi));
+            gap2 += g * g;
+            diag2 += (hi - lo) * (hi - lo);
+            ctr[c] = 0.5 * (lo + hi);
+        }
+        if (gap2 > diag2)  // a uniform branch
+            expanded_tile<R, SAFE>(L, O, jt, je, ctr, eps2, ftile, fmass);
+        else
+            quarter_tile<R, SAFE>(L, O, jt, je, wmin, wmax, eps2, eps2f, ftile, dtile);
+        __syncthreads();
+    }
+}
+
+// The sweep of a spatially ordered form: 4 quarter-tile, 5 hybrid.
+template <int R, bool SAFE, int FORM>
+__device__ __forceinline__ void form_sweep(Lane<P_MIXED, R> &L, const LocalSys &O, int64_t ib, int64_t jb,
+                                           int64_t je, double eps2, float eps2f, JL *ftile, JM *dtile,
+                                           float *fmass) {
+    if constexpr (FORM == 4)
+        quarter_sweep<R, SAFE>(L, O, ib, jb, je, eps2, eps2f, ftile, dtile);
+    else
+        hybrid_sweep<R, SAFE>(L, O, ib, jb, je, eps2, eps2f, ftile, dtile, fmass);
+}
+
+// One workgroup of a single-system launch in the shape of k_pair_local.
+template <int R, bool SAFE, int FORM>
+__device__ __forceinline__ void form_single(const PairLaunch &P, int64_t chunk, JL *ftile, JM *dtile,
+                                            float *fmass) {
     const int64_t n = P.sc.n;
     const LocalSys O{P.lo.px, P.lo.py, P.lo.pz, P.lo.pm, P.lo.tbox, n, P.lo.qbox};
     const int64_t ib = (P.i0 / (256 * R) + (int64_t)blockIdx.x) * (256 * R);
@@ -924,15 +1016,13 @@ __global__ __launch_bounds__(256) void k_pair_quarter(PairLaunch P, int64_t chun
     const int64_t je = (jb + chunk < n) ? jb + chunk : n;
     Lane<P_MIXED, R> L;
     lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, 256);
-    quarter_sweep<R, SAFE>(L, O, ib, jb, je, P.sc.eps2, P.sc.eps2f, ftile, dtile);
+    form_sweep<R, SAFE, FORM>(L, O, ib, jb, je, P.sc.eps2, P.sc.eps2f, ftile, dtile, fmass);
     local_rows<R>(L, ib, P.i0, P.i1, P.split, blockIdx.y, P.part, P.lo.perm, P.st, P.sc, P.kick, P.hdt);
 }
 
-// Batched, jsrc = 4: the items of k_pair_local_batched.
-template <int R, bool SAFE>
-__global__ __launch_bounds__(256) void k_pair_quarter_batched(BatchLaunch B) {
-    __shared__ JL ftile[256];
-    __shared__ JM dtile[256];
+// The items of a persistent batched launch, as k_pair_local_batched walks them.
+template <int R, bool SAFE, int FORM>
+__device__ __forceinline__ void form_batched(const BatchLaunch &B, JL *ftile, JM *dtile, float *fmass) {
     for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
         const WorkItem it = B.items[w];
         const SysConst sc = B.sys[it.sys];
@@ -945,14 +1035,46 @@ __global__ __launch_bounds__(256) void k_pair_quarter_batched(BatchLaunch B) {
         const int64_t je = (jb + ly.chunk < n) ? jb + ly.chunk : n;
         Lane<P_MIXED, R> L;
         lane_init<P_MIXED, R>(L, sorted_state(O), ib, n, 256);
-        quarter_sweep<R, SAFE>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile);
+        form_sweep<R, SAFE, FORM>(L, O, ib, jb, je, sc.eps2, sc.eps2f, ftile, dtile, fmass);
         // split partials are [split][4][n] from pbase; rows are the system's sorted positions
         local_rows<R>(L, ib, 0, n, ly.split, it.chunk, B.part + ly.pbase, B.lo.perm + off, B.st, sc,
                       B.kick_scale != 0.0, 0.5 * B.kick_scale * sc.dt);
     }
 }
 
-template <int R>
+// jsrc = 4, single system and batched.
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_quarter(PairLaunch P, int64_t chunk) {
+    __shared__ JL ftile[256];
+    __shared__ JM dtile[256];
+    form_single<R, SAFE, 4>(P, chunk, ftile, dtile, nullptr);
+}
+
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_quarter_batched(BatchLaunch B) {
+    __shared__ JL ftile[256];
+    __shared__ JM dtile[256];
+    form_batched<R, SAFE, 4>(B, ftile, dtile, nullptr);
+}
+
+// jsrc = 5, single system and batched.
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_hybrid(PairLaunch P, int64_t chunk) {
+    __shared__ JL ftile[256];
+    __shared__ JM dtile[256];
+    __shared__ float fmass[256];
+    form_single<R, SAFE, 5>(P, chunk, ftile, dtile, fmass);
+}
+
+template <int R, bool SAFE>
+__global__ __launch_bounds__(256) void k_pair_hybrid_batched(BatchLaunch B) {
+    __shared__ JL ftile[256];
+    __shared__ JM dtile[256];
+    __shared__ float fmass[256];
+    form_batched<R, SAFE, 5>(B, ftile, dtile, fmass);
+}
+
+template <int R, int FORM>
 hipError_t go_quarter(const PairLaunch &P, hipStream_t s) {
     const int64_t n = P.sc.n;
     const int64_t per = 256LL * R;
@@ -961,10 +1083,17 @@ hipError_t go_quarter(const PairLaunch &P, hipStream_t s) {
     const int64_t chunk = ((per_chunk + 255) / 256) * 256;
     if (nbx <= 0) return hipSuccess;
     dim3 grid((unsigned)nbx, (unsigned)P.split);
-    if (P.sc.safe32)
-        hipLaunchKernelGGL((k_pair_quarter<R, true>), grid, dim3(256), 0, s, P, chunk);
-    else
-        hipLaunchKernelGGL((k_pair_quarter<R, false>), grid, dim3(256), 0, s, P, chunk);
+    if constexpr (FORM == 4) {
+        if (P.sc.safe32)
+            hipLaunchKernelGGL((k_pair_quarter<R, true>), grid, dim3(256), 0, s, P, chunk);
+        else
+            hipLaunchKernelGGL((k_pair_quarter<R, false>), grid, dim3(256), 0, s, P, chunk);
+    } else {
+        if (P.sc.safe32)
+            hipLaunchKernelGGL((k_pair_hybrid<R, true>), grid, dim3(256), 0, s, P, chunk);
+        else
+            hipLaunchKernelGGL((k_pair_hybrid<R, false>), grid, dim3(256), 0, s, P, chunk);
+    }
     return hipGetLastError();
 }
 
@@ -988,7 +1117,8 @@ hipError_t pick_local(const PairLaunch &P, hipStream_t s) {
     if (P.sc.prec != P_MIXED || P.mode != MODE_ACC || P.block != 256 || P.i0 < 0 || P.i1 > P.sc.n ||
         P.i1 <= P.i0 || !P.lo.perm)
         return hipErrorInvalidValue;
-    if (P.jsrc == 4) return P.R == 1 ? go_quarter<1>(P, s) : (P.R == 2 ? go_quarter<2>(P, s) : hipErrorInvalidValue);
+    if (P.jsrc == 4) return P.R == 1 ? go_quarter<1, 4>(P, s) : (P.R == 2 ? go_quarter<2, 4>(P, s) : hipErrorInvalidValue);
+    if (P.jsrc == 5) return P.R == 1 ? go_quarter<1, 5>(P, s) : (P.R == 2 ? go_quarter<2, 5>(P, s) : hipErrorInvalidValue);
     const bool exp = P.jsrc == 3;
     if (P.R == 1) return exp ? go_local<1, true>(P, s) : go_local<1, false>(P, s);
     if (P.R == 2) return exp ? go_local<2, true>(P, s) : go_local<2, false>(P, s);
@@ -1176,21 +1306,33 @@ hipError_t go_local_batched(const BatchLaunch &B, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int R>
+template <int R, int FORM>
 hipError_t go_quarter_batched(const BatchLaunch &B, hipStream_t s) {
     if (B.nitems <= 0) return hipSuccess;
-    if (B.safe)
-        hipLaunchKernelGGL((k_pair_quarter_batched<R, true>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
-    else
-        hipLaunchKernelGGL((k_pair_quarter_batched<R, false>), dim3((unsigned)B.grid), dim3(256), 0, s, B);
+    const dim3 grid((unsigned)B.grid);
+    if constexpr (FORM == 4) {
+        if (B.safe)
+            hipLaunchKernelGGL((k_pair_quarter_batched<R, true>), grid, dim3(256), 0, s, B);
+        else
+            hipLaunchKernelGGL((k_pair_quarter_batched<R, false>), grid, dim3(256), 0, s, B);
+    } else {
+        if (B.safe)
+            hipLaunchKernelGGL((k_pair_hybrid_batched<R, true>), grid, dim3(256), 0, s, B);
+        else
+            hipLaunchKernelGGL((k_pair_hybrid_batched<R, false>), grid, dim3(256), 0, s, B);
+    }
     return hipGetLastError();
 }
 
-template <int R>
+template <int R, int FORM>
 int occ_quarter() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_quarter_batched<R, false>, 256, 0) != hipSuccess)
-        return 1;
+    hipError_t e;
+    if constexpr (FORM == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_quarter_batched<R, false>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair_hybrid_batched<R, false>, 256, 0);
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
@@ -1220,16 +1362,19 @@ int occ_prec(int R, int mode) {
 }  // namespace
 
 int pair_local_batched_occupancy(int R, int jsrc) {
-    if (jsrc == 4) return R == 2 ? occ_quarter<2>() : occ_quarter<1>();
+    if (jsrc == 4) return R == 2 ? occ_quarter<2, 4>() : occ_quarter<1, 4>();
+    if (jsrc == 5) return R == 2 ? occ_quarter<2, 5>() : occ_quarter<1, 5>();
     if (R == 2) return jsrc == 3 ? occ_local<2, true>() : occ_local<2, false>();
     return jsrc == 3 ? occ_local<1, true>() : occ_local<1, false>();
 }
 
 hipError_t launch_pair_local_batched(const BatchLaunch &B, int jsrc, hipStream_t s) {
     if (B.block != 256 || B.mode != MODE_ACC || B.prec != P_MIXED || !B.lay || !B.lo.perm) return hipErrorInvalidValue;
-    if (jsrc != 2 && jsrc != 3 && jsrc != 4) return hipErrorInvalidValue;
+    if (jsrc < 2 || jsrc > 5) return hipErrorInvalidValue;
     if (jsrc == 4)
-        return B.R == 1 ? go_quarter_batched<1>(B, s) : (B.R == 2 ? go_quarter_batched<2>(B, s) : hipErrorInvalidValue);
+        return B.R == 1 ? go_quarter_batched<1, 4>(B, s) : (B.R == 2 ? go_quarter_batched<2, 4>(B, s) : hipErrorInvalidValue);
+    if (jsrc == 5)
+        return B.R == 1 ? go_quarter_batched<1, 5>(B, s) : (B.R == 2 ? go_quarter_batched<2, 5>(B, s) : hipErrorInvalidValue);
     if (B.R == 1) return jsrc == 3 ? go_local_batched<1, true>(B, s) : go_local_batched<1, false>(B, s);
     if (B.R == 2) return jsrc == 3 ? go_local_batched<2, true>(B, s) : go_local_batched<2, false>(B, s);
     return hipErrorInvalidValue;
@@ -1253,14 +1398,14 @@ int pair_batched_occupancy(int prec, int R, int block, int mode) {
 }
 
 bool pair_config_supported(int prec, int R, int block, int jsrc, int mode) {
-    if (jsrc >= 2 && jsrc <= 4) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
+    if (jsrc >= 2 && jsrc <= 5) return prec == P_MIXED && mode == MODE_ACC && block == 256 && (R == 1 || R == 2);
     if (prec < 0 || prec > 2 || (jsrc != 0 && jsrc != 1)) return false;
     if (mode != MODE_ACC) return block == 256 && (R == 1 || R == 2);
     return (block == 128 || block == 256) && (R == 1 || R == 2 || R == 4);
 }
 
 hipError_t launch_pair(const PairLaunch &P, hipStream_t s) {
-    if (P.jsrc >= 2 && P.jsrc <= 4) return pick_local(P, s);
+    if (P.jsrc >= 2 && P.jsrc <= 5) return pick_local(P, s);
     switch (P.sc.prec) {
         case P_FP64: return pick_mode<P_FP64>(P, s);
         case P_MIXED: return pick_mode<P_MIXED>(P, s);

@@ -38,7 +38,7 @@ struct State {
     double *vx, *vy, *vz;
 };
 
-// Spatial order of one system (jsrc = 2, 3 and 4 plans): particles sorted
+// Spatial order of one system (jsrc = 2 to 5 plans): particles sorted
 // along a Morton curve, their positions and masses in that order, and a
 // bounding box (min x, y, z, max x, y, z) per tile of 256 sorted particles and
 // per quarter tile of 64 (quarter q of tile t at qbox[24 t + 6 q]).

@@ -1,5 +1,5 @@
 // Spatial order of one system for the local mixed pair sums (plans with
-// jsrc = 2, 3 and 4): particles sorted along a Morton (Z-order) curve of their
+// jsrc = 2 to 5): particles sorted along a Morton (Z-order) curve of their
 // positions, so that each tile of 256 consecutive sorted particles is
 // spatially compact, a bounding box per tile, and one per quarter tile (64
 // sorted particles, one wave's share of a tile).  The pair kernels then form

@@ -31,7 +31,7 @@
 using namespace nb;
 
 // Device scratch of nbody_accel_static, the entry point for callers that
-// cannot allocate: the spatial order (jsrc 2, 3 and 4 plans) and the split
+// cannot allocate: the spatial order (jsrc 2 to 5 plans) and the split
 // partial sums live here instead of in context-owned allocations.  Each GPU
 // that runs the library holds its own copy until the process ends.  Host code
 // never uses the array's name as an address: nbody_ctx_create resolves each
@@ -56,7 +56,7 @@ struct nbody_ctx {
     size_t phi_cap = 0;    // doubles
     double *integ = nullptr;  // Hermite predicted state / RK4 stages
     size_t integ_cap = 0;     // doubles
-    double *order = nullptr;  // spatial order of a system (jsrc 2, 3 and 4 plans)
+    double *order = nullptr;  // spatial order of a system (jsrc 2 to 5 plans)
     size_t order_cap = 0;     // doubles
     double *jvel = nullptr;   // velocities in that order (jerk plans with jsrc 2)
     size_t jvel_cap = 0;      // doubles
@@ -98,7 +98,7 @@ struct nbody_batch {
     size_t stage_cap = 0;
     hipEvent_t staged = nullptr;               // end of the last upload from `stage`
     // Batch plan: R targets per lane, 256 lanes, `split` = source tiles of 256
-    // per chunk (0: whole systems), jsrc = 0, 2, 3 or 4 for the NB_MIXED
+    // per chunk (0: whole systems), jsrc = 0 or 2 to 5 for the NB_MIXED
     // systems (2 and 3: spatial order).  Float32 systems never split.
     nbody_plan plan{1, 256, 32, 3};
     std::vector<BatchSys> lay;
@@ -324,7 +324,7 @@ PairLaunch make_pair_launch(const State &st, const SysConst &sc, int64_t i0, int
 }
 
 // Launches of one pair sum whose scratch is already in place: the spatial
-// order (jsrc 2, 3 and 4, into order_buf), the pair kernel, and the fixed-order
+// order (jsrc 2 to 5, into order_buf), the pair kernel, and the fixed-order
 // reduction of the split partial sums (P.part).
 nbody_status launch_pair_seq(nbody_ctx *ctx, PairLaunch &P, void *order_buf, hipStream_t s) {
     if (P.jsrc >= 2) {
@@ -352,7 +352,7 @@ nbody_status run_pair(nbody_ctx *ctx, const State &st, const SysConst &sc, int64
     if (P.jsrc >= 2) {
         // the rows of a spatially ordered plan are positions in its order
         if (!sorted_rows && (i0 != 0 || i1 != sc.n))
-            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2, 3 or 4) sums particle-index ranges of "
+            return fail(ctx, NB_ENOTSUP, "a spatially ordered plan (jsrc 2 to 5) sums particle-index ranges of "
                                          "whole systems only (nbody_accel_order_rows takes ranges of its order)");
         nbody_status r = ensure(ctx, &ctx->order, &ctx->order_cap, (local_order_bytes(sc.n) + 7) / 8, s);
         if (r != NB_OK) return r;
@@ -1006,18 +1006,18 @@ nbody_status nbody_spatial_order(nbody_ctx *ctx, const nbody_sys *sys, int32_t *
 // ---- batched ---------------------------------------------------------------
 
 // A batch sums its NB_MIXED systems in spatial order (batch plans with jsrc
-// 2, 3 or 4) from this size on; smaller systems have few source tiles far
+// 2 to 5) from this size on; smaller systems have few source tiles far
 // enough from a target tile for the tile-local forms and keep float64-formed
-// separations (LDS tiles).  The quarter-tile form (jsrc 4) finds far quarters
-// in smaller systems.
+// separations (LDS tiles).  The quarter-tile forms (jsrc 4 and 5) find far
+// quarters in smaller systems.
 constexpr int64_t kLocalMinN = 1 << 15;
 constexpr int64_t kQuarterMinN = 1 << 12;
 
-static int64_t local_min_n(int jsrc) { return jsrc == 4 ? kQuarterMinN : kLocalMinN; }
+static int64_t local_min_n(int jsrc) { return jsrc >= 4 ? kQuarterMinN : kLocalMinN; }
 
 static bool batch_plan_supported(const nbody_plan &pl) {
     return pl.block == 256 && (pl.R == 1 || pl.R == 2) && pl.split >= 0 && pl.split <= (1 << 20) &&
-           (pl.jsrc == 0 || (pl.jsrc >= 2 && pl.jsrc <= 4));
+           (pl.jsrc == 0 || (pl.jsrc >= 2 && pl.jsrc <= 5));
 }
 
 static hipError_t grow(nbody_batch *bt, nbody_batch::Buf &b, size_t bytes) {
@@ -1436,7 +1436,7 @@ static std::vector<nbody_plan> tune_candidates(nbody_ctx *ctx, int prec, int cls
     add(effective_plan(ctx, prec, cls, n));
     std::vector<int> jsrcs{0, 1};
     if (cls == NB_PLAN_JERK) jsrcs = prec == P_MIXED ? std::vector<int>{2, 0} : std::vector<int>{0};
-    else if (prec == P_MIXED && cls == NB_PLAN_ACCEL) jsrcs = {3, 2, 4, 0, 1};
+    else if (prec == P_MIXED && cls == NB_PLAN_ACCEL) jsrcs = {3, 5, 2, 4, 0, 1};
     // splits up to 64 while each chunk keeps at least two source tiles
     const int max_split = prec == P_FP32 ? 1 : 64;
     for (int jsrc : jsrcs)
@@ -1642,7 +1642,7 @@ nbody_status nbody_batch_autotune(nbody_ctx *ctx, nbody_batch *b, const nbody_sy
             nmax = std::max(nmax, c.n);
         }
         std::vector<nbody_plan> cand{b->plan};
-        for (int jsrc : any_mixed ? std::vector<int>{4, 3, 2, 0} : std::vector<int>{0})
+        for (int jsrc : any_mixed ? std::vector<int>{4, 5, 3, 2, 0} : std::vector<int>{0})
             for (int R : {1, 2})
                 for (int split : {0, 8, 16, 32, 64}) {
                     const nbody_plan c{R, 256, split, jsrc};

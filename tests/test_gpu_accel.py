@@ -246,8 +246,9 @@ def test_mass_patterns(nb, ctx, orc, prec, jsrc, pattern):
 # jsrc 2: far tiles subtract tile-local coordinates; jsrc 3: far tiles use the
 # expanded squared distance and the per-tile sum of the pair scales; jsrc 4:
 # the far test per wave and quarter tile, far quarters subtracting
-# coordinates relative to the quarter's centre
-LOCAL_PLANS = [dict(R=R, block=256, split=s, jsrc=j) for j in (2, 3, 4) for R in (1, 2) for s in (1, 3)]
+# coordinates relative to the quarter's centre; jsrc 5: far tiles as jsrc 3,
+# the others as jsrc 4
+LOCAL_PLANS = [dict(R=R, block=256, split=s, jsrc=j) for j in (2, 3, 4, 5) for R in (1, 2) for s in (1, 3)]
 
 
 @pytest.mark.parametrize("plan", LOCAL_PLANS, ids=lambda p: f"R{p['R']}s{p['split']}j{p['jsrc']}")
@@ -270,7 +271,7 @@ def test_mixed_tile_local(nb, ctx, orc, plan, model, n):
     assert e2["eps_cond"] <= MIXED_TOL["eps_cond"], e2
 
 
-@pytest.mark.parametrize("jsrc", [2, 3, 4])
+@pytest.mark.parametrize("jsrc", [2, 3, 4, 5])
 def test_mixed_tile_local_edges(nb, ctx, orc, jsrc):
     print(f"[case] mixed local edges jsrc={jsrc}", flush=True)
     plan = dict(R=2, block=256, split=2, jsrc=jsrc)

@@ -70,7 +70,8 @@ BATCH_PLANS = [None,  # the default plan
                {"R": 2, "block": 256, "split": 2, "jsrc": 0},
                {"R": 1, "block": 256, "split": 3, "jsrc": 3},
                {"R": 2, "block": 256, "split": 1, "jsrc": 2},
-               {"R": 2, "block": 256, "split": 3, "jsrc": 4}]
+               {"R": 2, "block": 256, "split": 3, "jsrc": 4},
+               {"R": 1, "block": 256, "split": 2, "jsrc": 5}]
 
 
 def plan_id(p):
@@ -213,7 +214,8 @@ LARGE_SPECS = [
                                    {"R": 2, "block": 256, "split": 0, "jsrc": 2},
                                    {"R": 1, "block": 256, "split": 7, "jsrc": 2},
                                    {"R": 2, "block": 256, "split": 16, "jsrc": 4},
-                                   {"R": 1, "block": 256, "split": 0, "jsrc": 4}], ids=plan_id)
+                                   {"R": 1, "block": 256, "split": 0, "jsrc": 4},
+                                   {"R": 2, "block": 256, "split": 8, "jsrc": 5}], ids=plan_id)
 def test_spatial_order_batch_large_systems(nb, ctx, orc, bplan):
     # mixed systems of 2^15 particles or more (2^12 under the quarter-tile
     # form) are summed in their own spatial order inside the batch (the
@@ -235,8 +237,8 @@ def test_spatial_order_batch_large_systems(nb, ctx, orc, bplan):
         for k, (sp, ic, prm) in enumerate(zip(LARGE_SPECS, parts, prms)):
             lo, hi = off[k], off[k + 1]
             plan = nb.nbody_batch_system_plan(ctx, b, k)
-            # spatial order from 2^15 particles on (2^12 for the quarter-tile form)
-            if sp[4] == "mixed" and sp[1] >= (1 << 12 if bplan["jsrc"] == 4 else 1 << 15):
+            # spatial order from 2^15 particles on (2^12 for the quarter-tile forms)
+            if sp[4] == "mixed" and sp[1] >= (1 << 12 if bplan["jsrc"] >= 4 else 1 << 15):
                 assert plan["jsrc"] == bplan["jsrc"], (k, plan)
             elif sp[1] > 0:
                 assert plan["jsrc"] == 0, (k, plan)

@@ -70,11 +70,12 @@ def test_disk_2p20_sampled(nb, ctx, orc, disk20, prec):
         assert net <= 1e-13 * scale, (net, scale)
 
 
-# the quarter-tile form (jsrc 4) at the sizes and splits of the tuned mixed
-# plans, on the same sampled rows and gate
+# the quarter-tile forms (jsrc 4 and 5) at the sizes and splits of the tuned
+# mixed plans, on the same sampled rows and gate
 @pytest.mark.parametrize("log2n,plan", [(20, {"R": 1, "block": 256, "split": 32, "jsrc": 4}),
-                                        (17, {"R": 2, "block": 256, "split": 16, "jsrc": 4})],
-                         ids=["2p20R1s32", "2p17R2s16"])
+                                        (17, {"R": 2, "block": 256, "split": 16, "jsrc": 4}),
+                                        (20, {"R": 1, "block": 256, "split": 16, "jsrc": 5})],
+                         ids=["2p20R1s32", "2p17R2s16", "2p20R1s16j5"])
 def test_disk_quarter_plan_sampled(nb, ctx, orc, disk20, log2n, plan):
     n = 1 << log2n
     print(f"[case] disk 2^{log2n} mixed quarter-tile plan {plan} sampled rows", flush=True)

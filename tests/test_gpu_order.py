@@ -135,7 +135,8 @@ def test_capture_refuses_to_grow_scratch(nb, ctx):
 
 @pytest.mark.parametrize("plan", [{"R": 1, "block": 256, "split": 4, "jsrc": 3},
                                   {"R": 2, "block": 256, "split": 1, "jsrc": 2},
-                                  {"R": 2, "block": 256, "split": 3, "jsrc": 4}], ids=["R1s4j3", "R2s1j2", "R2s3j4"])
+                                  {"R": 2, "block": 256, "split": 3, "jsrc": 4},
+                                  {"R": 1, "block": 256, "split": 2, "jsrc": 5}], ids=["R1s4j3", "R2s1j2", "R2s3j4", "R1s2j5"])
 def test_order_rows_bitwise(nb, ctx, plan):
     # the i-split under a spatially ordered plan: ranges of the Morton order
     # give the full launch's bits for their particles and touch no others;

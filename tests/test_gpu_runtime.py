@@ -161,7 +161,7 @@ def test_plan_classes(nb, ctx, orc):
                           (nb.NB_FP32, {"R": 1, "block": 256, "split": 1, "jsrc": 2}),
                           (nb.NB_MIXED, {"R": 4, "block": 256, "split": 1, "jsrc": 3}),
                           (nb.NB_MIXED, {"R": 1, "block": 128, "split": 1, "jsrc": 2}),
-                          (nb.NB_MIXED, {"R": 1, "block": 256, "split": 1, "jsrc": 5}),
+                          (nb.NB_MIXED, {"R": 1, "block": 256, "split": 1, "jsrc": 6}),
                           (nb.NB_MIXED | nb.NB_PLAN_JERK, {"R": 1, "block": 256, "split": 1, "jsrc": 4}),
                           (nb.NB_MIXED | nb.NB_PLAN_POTENTIAL, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
                           (nb.NB_MIXED | nb.NB_PLAN_JERK, {"R": 1, "block": 256, "split": 1, "jsrc": 3}),
@@ -218,7 +218,7 @@ def test_autotune_finds_the_headline_plan_class(nb, ctx, orc):
     try:
         tuned = nb.nbody_autotune_sys(ctx, nb.NB_MIXED, s, prm, 0.0)
         print(f"[tune] 2^17 mixed: tuned {tuned}, committed {committed}", flush=True)
-        assert tuned["jsrc"] in (2, 3, 4), tuned
+        assert tuned["jsrc"] in (2, 3, 4, 5), tuned
         assert nb.nbody_plan_get(ctx, nb.NB_MIXED, n) == tuned
         rows = np.sort(np.random.default_rng(8).choice(n, size=512, replace=False))
         ax, ay, az, A = orc.accel(ic["x"], ic["y"], ic["z"], ic["m"], 1.0, 0.02, rows=rows, want_scale=True)

@@ -3,13 +3,13 @@
 for their kernel class and precision, as documented for nbody_plan and the
 NB_PLAN_* classes in include/nbody.h:
   * acceleration sum: R 1, 2 or 4; 128 or 256 lanes; split >= 1 (1 for
-    float32); jsrc 0 or 1, or 2 / 3 / 4 (spatial order) for mixed with 256
+    float32); jsrc 0 or 1, or 2 to 5 (spatial order) for mixed with 256
     lanes and R 1 or 2;
   * potential pass: 256 lanes, R 1 or 2, jsrc 0 or 1;
   * acceleration-and-jerk sum: 256 lanes, R 1 or 2, jsrc 0, or 2 (spatial
     order) for mixed;
   * batch plans (mixed/batch, keyed by the largest system): 256 lanes, R 1 or
-    2, split = source tiles per chunk >= 0 (0: whole systems), jsrc 0, 2, 3 or 4.
+    2, split = source tiles per chunk >= 0 (0: whole systems), jsrc 0 or 2 to 5.
 A bad entry would make load_plans fail on the GPU; this checks the file on
 the host.  Keys are ceil(log2 n) of the size class."""
 import json
@@ -23,14 +23,14 @@ def _ok(prec: str, cls: str, p: dict) -> bool:
     R, block, split, jsrc = p["R"], p["block"], p["split"], p["jsrc"]
     if cls == "batch":
         return (prec == "mixed" and block == 256 and R in (1, 2) and isinstance(split, int)
-                and 0 <= split <= (1 << 20) and jsrc in (0, 2, 3, 4))
+                and 0 <= split <= (1 << 20) and jsrc in (0, 2, 3, 4, 5))
     if not (isinstance(split, int) and 1 <= split <= 1024):
         return False
     if cls == "jerk":
         return block == 256 and R in (1, 2) and (jsrc == 0 or (jsrc == 2 and prec == "mixed"))
     if cls == "potential":
         return block == 256 and R in (1, 2) and jsrc in (0, 1)
-    if jsrc in (2, 3, 4):
+    if jsrc in (2, 3, 4, 5):
         return prec == "mixed" and block == 256 and R in (1, 2)
     if prec == "fp32" and split != 1:
         return False
@@ -72,9 +72,10 @@ def test_plan_rule_rejects_known_bad_plans():
         ("fp32", "accel", dict(good, jsrc=2)),
         ("mixed", "accel", dict(good, R=4, jsrc=3)),
         ("mixed", "accel", dict(good, block=128, jsrc=2)),
-        ("mixed", "accel", dict(good, jsrc=5)),
+        ("mixed", "accel", dict(good, jsrc=6)),
         ("mixed", "jerk", dict(good, jsrc=4)),
-        ("mixed", "batch", dict(good, jsrc=5)),
+        ("mixed", "jerk", dict(good, jsrc=5)),
+        ("mixed", "batch", dict(good, jsrc=6)),
         ("fp32", "accel", dict(good, split=2)),
         ("fp64", "potential", dict(good, jsrc=2)),
         ("fp64", "potential", dict(good, block=128)),
