@@ -77,7 +77,7 @@ def test_flat_system_and_zero_extent(nb, ctx):
 
 @pytest.mark.parametrize("kind", ["accel", "jerk"])
 def test_spatial_plan_graph_capture_matches_eager(nb, ctx, kind):
-    # the tuned mixed plans at N = 2^17 (spatial order, 32-way split):
+    # the tuned mixed plans at N = 2^17 (spatial order, split sums):
     # KDK (or Hermite) steps captured in a graph replay bitwise like eager calls
     n = 1 << 17
     print(f"[case] graph capture spatial plan {kind} n={n}", flush=True)
