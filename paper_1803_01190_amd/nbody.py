@@ -283,7 +283,7 @@ def nbody_surface_density(ctx, sys: System, nx: int, ny: int, x0: float, y0: flo
 
 
 def nbody_spatial_order(ctx, sys: System, stream=None):
-    """(perm, keys): the Morton order of the jsrc 2/3 plans as device tensors
+    """(perm, keys): the Morton order of the spatially ordered plans (jsrc 2 to 5) as device tensors
     (int32 permutation; the sorted uint64 keys held in an int64 tensor)."""
     dev = sys.t["x"].device
     perm = torch.empty(sys.n, dtype=torch.int32, device=dev)

@@ -1,4 +1,4 @@
-"""The spatial (Morton) order behind the jsrc 2 and 3 plans is computed by
+"""The spatial (Morton) order behind the jsrc 2 to 5 plans is computed by
 the library's own kernels (bounding box, keys, an eight-pass stable radix
 sort, gathers).  Its permutation must be exactly the stable sort of the keys
 that nbody_spatial_order's contract defines, recomputed here on the host; and
